@@ -1,0 +1,46 @@
+"""Single-particle SEEA prediction (Section 3, Eq 19-20 and the flux
+estimate of Section 4).  Test infrastructure only (see ``oracle/__init__``).
+
+A secondary electron leaves the surface with energy A0 along the normal,
+is pulled back by the surface-charge field a_ex and accelerated along the
+surface by a_ey; in a saturated avalanche it must return with the energy A1
+at which the yield is one.  With E_x = sigma / 2 eps0 at the surface and the
+cosine-averaged launch, this fixes sigma (Eq 20).  Readings: A0 = T_se and
+A1 is the first normal-incidence crossover of the Eq 8-9 yield curve.
+"""
+import math
+
+from scipy.optimize import brentq
+
+from .solver import E_CHARGE, EPS0, M_E, sey
+
+
+def first_crossover_ev(delta_max, a_max_ev, ks=1.0):
+    """Smallest energy with yield one at normal incidence, or None when the
+    curve never reaches one (delta_max <= 1: no avalanche can form)."""
+    peak = a_max_ev
+    if sey(delta_max, a_max_ev, ks, peak, 0.0) <= 1.0:
+        return None
+    return brentq(lambda a: sey(delta_max, a_max_ev, ks, a, 0.0) - 1.0, 1e-9 * peak, peak,
+                  xtol=1e-14, rtol=1e-14, maxiter=500)
+
+
+def sigma_saturated(ey, delta_max, a_max_ev, a0_ev, ks=1.0):
+    """Eq 20: sigma = 2 eps0 |E_y| [ (A1/A0 - 1) / 2 ]^(-1/2), C/m^2."""
+    a1 = first_crossover_ev(delta_max, a_max_ev, ks)
+    if a1 is None or a1 <= a0_ev:
+        return None
+    return 2.0 * EPS0 * abs(ey) * (0.5 * (a1 / a0_ev - 1.0)) ** -0.5
+
+
+def flight_time(sigma, a0_ev):
+    """Time of flight of a normally launched secondary, 2 v0 / |a_ex| with
+    a_ex = e E_x / m and E_x = sigma / 2 eps0."""
+    v0 = math.sqrt(2.0 * a0_ev * E_CHARGE / M_E)
+    aex = E_CHARGE * (sigma / (2.0 * EPS0)) / M_E
+    return 2.0 * v0 / aex
+
+
+def primary_flux_saturated(sigma, a0_ev):
+    """Flux estimate Gamma_pe = sigma / (e t_ef) (Section 4)."""
+    return sigma / (E_CHARGE * flight_time(sigma, a0_ev))
