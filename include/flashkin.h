@@ -1,0 +1,216 @@
+/*
+ * flashkin.h -- C-ABI of the MI355X (gfx950) library that advances the
+ * 1D2V electron distribution of the vacuum surface-flashover model of
+ * Sun et al., "An alternative simulation approach for surface flashover in
+ * vacuum using a 1D2V continuum and kinetic model" (arXiv 2303.14119).
+ *
+ * One step (Section 2) advances f(x, v_x, v_y) on a cell-centred phase-space
+ * grid by explicit first-order upwind transport (the paragraph after Eq 2):
+ * x by v_x, then v_x by a_x = -e E_x(x)/m, then v_y by a_y = -e E_y/m, then
+ * the field-emission band source (Eq 7).  At the dielectric (x = 0) the
+ * primary flux (Eq 13-14) is absorbed, secondaries are re-emitted through
+ * the SEE yield matrix (Eq 8-12) with the half-Maxwellian of Eq 15-16, and
+ * the surface charge is updated by Eq 18.  Everything reaching x = L is
+ * absorbed (Eq 17).  E_x comes from the 1D Gauss law with
+ * E_x(0) = sigma / 2 eps0 (the paragraph on the velocity advections).
+ *
+ * Conventions for every call:
+ *   - Return value: FK_OK (0) or a negative FK_E_* code.  No C++ exception
+ *     crosses this boundary.  fk_last_error() gives a message.
+ *   - Device pointers are HIP device addresses on the current device; host
+ *     pointers are ordinary process memory.  Nothing passed in is freed by
+ *     the library unless the call says so.
+ *   - A context is not thread-safe: one host thread at a time per context.
+ *   - Work is queued on the HIP stream given at creation (NULL = the null
+ *     stream).  Calls that return data to the host synchronise that stream.
+ *   - f is laid out [k][i][j] (x index k slowest, v_y index j fastest),
+ *     dense, element type FK_F32 (float) or FK_F64 (double).
+ *   - Units are SI; energies and temperatures named *_ev are in eV.
+ */
+#ifndef FLASHKIN_H
+#define FLASHKIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FK_ABI_VERSION 1u
+
+/* element type of f */
+enum { FK_F32 = 0, FK_F64 = 1 };
+
+/* normalisation of the emission row (Eq 15-16) */
+enum {
+    FK_EMIT_DISCRETE = 0, /* scaled so the emitted flux on the grid equals Gamma_see */
+    FK_EMIT_ANALYTIC = 1  /* the continuum prefactor of Eq 15 */
+};
+
+/* parts of the step (all on = FK_PHYS_ALL); tests switch parts off */
+enum {
+    FK_PHYS_X = 1,           /* x advection with the wall and vacuum boundaries */
+    FK_PHYS_VX = 2,          /* v_x advection by -e E_x / m */
+    FK_PHYS_VY = 4,          /* v_y advection by -e E_y / m */
+    FK_PHYS_SRC = 8,         /* band source (Eq 7) */
+    FK_PHYS_SEE = 16,        /* secondary emission (Eq 8-16) */
+    FK_PHYS_SELF_FIELD = 32, /* E_x from sigma and the electron space charge */
+    FK_PHYS_ALL = 63
+};
+
+/* error codes */
+enum {
+    FK_OK = 0,
+    FK_E_INVALID = -1,   /* bad argument or parameter */
+    FK_E_OOM = -2,       /* device or host allocation failed */
+    FK_E_HIP = -3,       /* a HIP runtime call failed */
+    FK_E_CFL = -4,       /* a Courant number exceeded one (sticky until fk_write_state) */
+    FK_E_NONFINITE = -5, /* a moment or flux became NaN/Inf (sticky until fk_write_state) */
+    FK_E_STATE = -6      /* call not valid in the object's current state */
+};
+
+/* Parameters of one run.  Set struct_size = sizeof(fk_params) and
+ * abi_version = FK_ABI_VERSION.  Inputs of Section 2's parameter list. */
+typedef struct {
+    uint32_t struct_size, abi_version;
+    int32_t nx, nvx, nvy;    /* cells in x (normal to the surface), v_x, v_y; each >= 1, nvy <= 1024 */
+    int32_t dtype;           /* FK_F32 or FK_F64 */
+    double length_m;         /* domain extent normal to the surface (x in [0, L]) */
+    double vmax_x, vmax_y;   /* velocity box [-vmax, vmax] in each direction, m/s */
+    double dt;               /* time step, s; 0 selects cfl * min(dx/vmax_x, dv_x/|a_y|, dv_y/|a_y|) */
+    double cfl;              /* CFL fraction used when dt = 0 */
+    double ey;               /* applied tangential field E_y, V/m (negative: cathode on the left) */
+    double delta_max;        /* SEY maximum (Eq 8) */
+    double a_max_ev;         /* normal-incidence energy of the SEY maximum (Eq 9) */
+    double ks;               /* surface smoothness factor k_s (Eq 8-9), 1 for a normal surface */
+    double t_se_ev;          /* secondary emission temperature T_se (Eq 15) */
+    double j_src;            /* seed current density of the band source, A/m^2 (Eq 7) */
+    double x_src_lo, x_src_hi; /* source band in x, m (the paper: 10-15 um) */
+    double t_src_ev;         /* temperature of the source VDF (Eq 7) */
+    int32_t emission_norm;   /* FK_EMIT_DISCRETE or FK_EMIT_ANALYTIC */
+    uint32_t physics_mask;   /* FK_PHYS_* bits */
+    double ex_external;      /* uniform E_x added to the self field, V/m */
+    int32_t trace_stride;    /* record observables every trace_stride steps (>= 1) */
+    int32_t trace_cap;       /* records held on the device between drains (>= 1) */
+    int32_t tile_rows;       /* v_x rows per tile, 0 = library choice */
+    int32_t tile_planes;     /* x planes per tile, 0 = library choice */
+} fk_params;
+
+/* Observables of the state (f^n, sigma^n) after n steps.  The fluxes are
+ * those of f^n, i.e. the ones step n+1 will use. */
+typedef struct {
+    int64_t step;            /* n */
+    double t;                /* n dt, s */
+    double sigma;            /* surface charge sigma^n, C/m^2 (Eq 18) */
+    double sigma_lo;         /* compensation term of the sigma sum (sigma + sigma_lo is the value) */
+    double g_pe;             /* primary flux into the wall, 1/(m^2 s) (Eq 13-14) */
+    double g_see;            /* secondary flux (Eq 12, 14) */
+    double g_top;            /* flux leaving through x = L */
+    double emitted;          /* flux carried by the emission row, sum v_x f_ghost dv_x dv_y */
+    double loss_v;           /* electrons/m^2 lost through the velocity-box edges in step n */
+    double n_total;          /* electrons/m^2 in the domain */
+    double resid;            /* particle balance residual of step n, electrons/m^2 */
+} fk_state;
+
+/* Derived quantities of a parameter set. */
+typedef struct {
+    double dx, dvx, dvy, dt;
+    double courant_x;        /* max |v_x| dt / dx over the grid */
+    double courant_vy;       /* |a_y| dt / dv_y */
+    int64_t cells;           /* nx * nvx * nvy */
+    int32_t tile_rows, tile_planes, block, n_tiles;
+    uint64_t bytes_device;   /* device memory the context allocates */
+} fk_info;
+
+typedef struct fk_ctx fk_ctx;
+typedef struct fk_batch fk_batch;
+
+/* Error text for a code; and the last message of a context (NULL: of the
+ * calling thread's last failed create). */
+const char* fk_error_string(int code);
+const char* fk_last_error(const fk_ctx* ctx);
+
+/* Validate a parameter set and derive grid spacings, time step and launch
+ * shape.  Host only; does not touch the GPU.  out may be NULL. */
+int fk_validate(const fk_params* p, fk_info* out);
+
+/* Create a context: builds the grids and the tables of Eq 7, 8-11 and 15 on
+ * the device, sets f = 0, sigma = 0, step 0.  stream is a hipStream_t (or
+ * NULL).  The context owns its device memory. */
+int fk_create(const fk_params* p, void* stream, fk_ctx** out);
+
+/* As fk_create, but f lives in two caller-owned device buffers of
+ * nx*nvx*nvy elements each (ping-pong).  The caller keeps them alive and
+ * does not touch them until fk_destroy. */
+int fk_create_borrowed(const fk_params* p, void* stream, void* f_a, void* f_b, fk_ctx** out);
+
+int fk_destroy(fk_ctx* ctx);
+
+/* Derived quantities of the context's parameters. */
+int fk_query(const fk_ctx* ctx, fk_info* out);
+
+/* Queue nsteps >= 0 steps on the stream (asynchronous).  Returns a sticky
+ * error seen by an earlier fk_sync. */
+int fk_step(fk_ctx* ctx, int64_t nsteps);
+
+/* Wait for queued work; returns FK_E_CFL or FK_E_NONFINITE if a step raised
+ * one since the last fk_write_state. */
+int fk_sync(fk_ctx* ctx);
+
+/* Copy the current f (layout and type as above) to dst, which holds
+ * dst_bytes >= nx*nvx*nvy*sizeof(element) bytes; on the device if
+ * dst_on_device != 0, else in host memory. */
+int fk_read_f(fk_ctx* ctx, void* dst, size_t dst_bytes, int dst_on_device);
+
+/* Observables of the current state (synchronises). */
+int fk_read_state(fk_ctx* ctx, fk_state* out);
+
+/* E_x at the nx cell centres (V/m) and n_e (1/m^3) of the current state;
+ * either pointer may be NULL.  Host memory unless dst_on_device != 0.
+ * The x-resolved enclosed charge is 2 eps0 E_x. */
+int fk_read_field(fk_ctx* ctx, double* ex, double* ne, int dst_on_device);
+
+/* Host copies of the FP64 tables: delta (Eq 8-11, 0 where v_x >= 0), the
+ * emission shape exp(-m v^2 / 2 T_se) (0 where v_x <= 0), the normalised
+ * source VDF (nvx*nvy each, [i][j]) and the band weights (nx).  Any pointer
+ * may be NULL. */
+int fk_read_tables(fk_ctx* ctx, double* delta, double* ghat, double* fsrc, double* wband);
+
+/* Drain the trace ring: copies up to cap records made since the last drain
+ * (oldest first) to dst (host), count in *n_out.  If more than trace_cap
+ * records were made since the last drain, only the newest trace_cap remain
+ * and the call returns FK_E_STATE after copying them. */
+int fk_read_trace(fk_ctx* ctx, fk_state* dst, size_t cap, size_t* n_out);
+
+/* Replace the state: f (NULL keeps the current f; device memory if
+ * src_on_device, else host), sigma = sigma + sigma_lo, and the step counter.
+ * Clears sticky errors and the trace history.  Used for warm starts,
+ * checkpoint restore and tests. */
+int fk_write_state(fk_ctx* ctx, const void* f, int src_on_device, double sigma, double sigma_lo,
+                   int64_t step);
+
+/* Saturation test of Section 2 (sigma, Gamma_pe and Gamma_see each change
+ * by at most rtol relative within a window of window_s seconds), applied to
+ * the trace history drained so far (the call drains the ring first).
+ * *out = 1 if saturated, 0 if not or if the history is shorter than the
+ * window. */
+int fk_saturated(fk_ctx* ctx, double window_s, double rtol, int* out);
+
+/* The same test on a caller-held trace (host only, no GPU). */
+int fk_saturation_check(const fk_state* trace, size_t n, double window_s, double rtol, int* out);
+
+/* Kernel timing.  While profiling is on, fk_step launches without graphs
+ * and brackets every launch with HIP events on the context's stream;
+ * fk_kernel_times synchronises and returns the summed milliseconds and the
+ * launch counts of the sweep kernel and of the reduction/field kernel since
+ * profiling was switched on. */
+int fk_set_profiling(fk_ctx* ctx, int on);
+int fk_kernel_times(fk_ctx* ctx, double* sweep_ms, int64_t* sweep_count, double* field_ms,
+                    int64_t* field_count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FLASHKIN_H */

@@ -116,8 +116,11 @@ double orc_sey(double delta_max, double a_max_ev, double ks, double a_in_ev, dou
 static void build_tables(orc_sim* s)
 {
     const orc_params* p = &s->p;
-    for (int i = 0; i < p->nvx; ++i) s->vx[i] = -p->vmax_x + (i + 0.5) * s->dvx;
-    for (int j = 0; j < p->nvy; ++j) s->vy[j] = -p->vmax_y + (j + 0.5) * s->dvy;
+    /* cell centres of [-vmax, vmax]: (i + 1/2 - N/2) dv, which is the same
+       number as -vmax + (i + 1/2) dv but exact in sign, so the middle cell of
+       an odd grid is exactly v = 0 and opposite cells are exact negatives */
+    for (int i = 0; i < p->nvx; ++i) s->vx[i] = (i + 0.5 - 0.5 * p->nvx) * s->dvx;
+    for (int j = 0; j < p->nvy; ++j) s->vy[j] = (j + 0.5 - 0.5 * p->nvy) * s->dvy;
 
     double zsum = 0.0, srcsum = 0.0;
     for (int i = 0; i < p->nvx; ++i) {

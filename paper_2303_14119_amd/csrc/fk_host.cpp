@@ -1,0 +1,170 @@
+// fk_host.cpp -- host-only parts of the C-ABI: parameter validation, the
+// derived layout, error strings and the saturation test.  Nothing here
+// touches the GPU, so these calls work on machines without one.
+#include <cmath>
+#include <cstring>
+
+#include "fk_internal.h"
+
+namespace fk {
+
+static thread_local std::string g_create_error;
+
+const char* global_error() { return g_create_error.c_str(); }
+
+int set_error(std::string* slot, int code, const std::string& msg)
+{
+    if (slot) *slot = msg;
+    else g_create_error = msg;
+    return code;
+}
+
+static size_t sweep_lds(int ti, int block, int kc, int elem)
+{
+    const int waves = (block + 63) / 64;
+    return (size_t)2 * ti * (block + 2) * elem + (size_t)kc * waves * 8 + (size_t)waves * 4 * 8;
+}
+
+int derive_layout(const fk_params* p, Layout* L, std::string* why)
+{
+    auto bad = [&](const char* m) { if (why) *why = m; return FK_E_INVALID; };
+    if (!p) return bad("params is NULL");
+    if (p->struct_size != sizeof(fk_params)) return bad("params.struct_size != sizeof(fk_params)");
+    if (p->abi_version != FK_ABI_VERSION) return bad("params.abi_version does not match FK_ABI_VERSION");
+    if (p->nx < 1 || p->nvx < 1 || p->nvy < 1) return bad("nx, nvx and nvy must be >= 1");
+    if (p->nvy > 1024) return bad("nvy must be <= 1024 (one v_y column per thread of a workgroup)");
+    if (p->dtype != FK_F32 && p->dtype != FK_F64) return bad("dtype must be FK_F32 or FK_F64");
+    if (!(p->length_m > 0) || !(p->vmax_x > 0) || !(p->vmax_y > 0)) return bad("length_m, vmax_x, vmax_y must be > 0");
+    if (!(p->dt >= 0) || !std::isfinite(p->dt)) return bad("dt must be >= 0 and finite");
+    if (p->dt == 0 && !(p->cfl > 0 && p->cfl <= 1)) return bad("cfl must be in (0, 1] when dt = 0");
+    if (!std::isfinite(p->ey) || !std::isfinite(p->ex_external)) return bad("fields must be finite");
+    if (!(p->delta_max >= 0) || !(p->a_max_ev > 0) || !(p->ks >= 0)) return bad("SEY parameters out of range");
+    if (!(p->t_se_ev > 0) || !(p->t_src_ev > 0)) return bad("temperatures must be > 0");
+    if (!(p->j_src >= 0) || !std::isfinite(p->j_src)) return bad("j_src must be >= 0");
+    if (!(p->x_src_hi >= p->x_src_lo)) return bad("x_src_hi must be >= x_src_lo");
+    if (p->emission_norm != FK_EMIT_DISCRETE && p->emission_norm != FK_EMIT_ANALYTIC) return bad("bad emission_norm");
+    if (p->physics_mask & ~(uint32_t)FK_PHYS_ALL) return bad("unknown physics_mask bits");
+    if (p->trace_stride < 1 || p->trace_cap < 1) return bad("trace_stride and trace_cap must be >= 1");
+    if (p->tile_rows != 0 && p->tile_rows != 4 && p->tile_rows != 8 && p->tile_rows != 16)
+        return bad("tile_rows must be 0, 4, 8 or 16");
+    if (p->tile_planes < 0 || p->tile_planes > 128) return bad("tile_planes must be in [0, 128]");
+
+    const int64_t cells = (int64_t)p->nx * p->nvx * p->nvy;
+    if (cells > ((int64_t)1 << 40)) return bad("grid too large");
+
+    Layout l{};
+    l.cells = cells;
+    l.elem = p->dtype == FK_F32 ? 4 : 8;
+    l.dx = p->length_m / p->nx;
+    l.dvx = 2.0 * p->vmax_x / p->nvx;
+    l.dvy = 2.0 * p->vmax_y / p->nvy;
+    const double ay = -kE * p->ey / kMe;
+    if (p->dt > 0) {
+        l.dt = p->dt;
+    } else {
+        double tmin = l.dx / p->vmax_x;
+        if (ay != 0) {
+            tmin = std::fmin(tmin, l.dvx / std::fabs(ay));
+            tmin = std::fmin(tmin, l.dvy / std::fabs(ay));
+        }
+        l.dt = p->cfl * tmin;
+    }
+    const double vx_edge = p->vmax_x - 0.5 * l.dvx;   // largest |v_x| of a cell centre
+    l.courant_x = (p->physics_mask & FK_PHYS_X) ? vx_edge * l.dt / l.dx : 0.0;
+    l.dy = (p->physics_mask & FK_PHYS_VY) ? ay * l.dt / l.dvy : 0.0;
+    l.courant_vy = std::fabs(l.dy);
+    if (l.courant_x > 1.0) { if (why) *why = "x Courant number exceeds 1"; return FK_E_CFL; }
+    if (l.courant_vy > 1.0) { if (why) *why = "v_y Courant number exceeds 1"; return FK_E_CFL; }
+
+    // launch shape: one thread per v_y column; tiles of ti v_x rows and kc x planes
+    l.block = ((p->nvy + 63) / 64) * 64;
+    int ti = p->tile_rows;
+    if (ti == 0) {
+        if (l.elem == 4) ti = l.block <= 512 ? 16 : 8;
+        else ti = l.block <= 512 ? 8 : 4;
+        while (ti > 4 && sweep_lds(ti, l.block, 128, l.elem) > kLdsBudget) ti /= 2;
+    }
+    if (ti == 16 && (l.elem != 4 || l.block > 512)) return bad("tile_rows 16 needs FK_F32 and nvy <= 512");
+    if (ti == 8 && l.elem == 8 && l.block > 512) return bad("tile_rows 8 with FK_F64 needs nvy <= 512");
+    l.ti = ti;
+    l.n_it = (p->nvx + ti - 1) / ti;
+    int kc = p->tile_planes;
+    if (kc == 0) {
+        // enough workgroups to fill 256 compute units several times over,
+        // but long enough x runs that the halo planes stay a small overhead
+        const int target = 2048;
+        int nkc = (target + l.n_it - 1) / l.n_it;
+        kc = (p->nx + nkc - 1) / nkc;
+        if (kc < 4) kc = 4;
+        if (kc > 128) kc = 128;
+    }
+    if (kc > p->nx) kc = p->nx;
+    l.kc = kc;
+    l.n_kc = (p->nx + kc - 1) / kc;
+    l.nwg = l.n_it * l.n_kc;
+    l.lds_sweep = sweep_lds(ti, l.block, kc, l.elem);
+    l.lds_moments = (size_t)kc * (l.block / 64) * 8 + (size_t)(l.block / 64) * 4 * 8;
+    if (l.lds_sweep > kLdsBudget) return bad("tile needs more LDS than a workgroup has; lower tile_rows or tile_planes");
+
+    const uint64_t v2 = (uint64_t)p->nvx * p->nvy;
+    l.bytes_device = 2ull * cells * l.elem + v2 * (8 * 3 + l.elem) + (uint64_t)p->nx * 8 * 6 +
+                     (uint64_t)p->nx * l.n_it * 8 + (uint64_t)l.n_it * 24 + (uint64_t)l.nwg * 8 +
+                     sizeof(DevState) + (uint64_t)p->trace_cap * sizeof(fk_state) + 64;
+    *L = l;
+    return FK_OK;
+}
+
+}  // namespace fk
+
+using namespace fk;
+
+extern "C" const char* fk_error_string(int code)
+{
+    switch (code) {
+    case FK_OK: return "ok";
+    case FK_E_INVALID: return "invalid argument";
+    case FK_E_OOM: return "out of memory";
+    case FK_E_HIP: return "HIP runtime error";
+    case FK_E_CFL: return "Courant number above one";
+    case FK_E_NONFINITE: return "non-finite moment or flux";
+    case FK_E_STATE: return "call not valid in the current state";
+    default: return "unknown error";
+    }
+}
+
+extern "C" int fk_validate(const fk_params* p, fk_info* out)
+{
+    Layout L;
+    std::string why;
+    int rc = derive_layout(p, &L, &why);
+    if (rc != FK_OK) return set_error(nullptr, rc, why);
+    if (out) {
+        out->dx = L.dx; out->dvx = L.dvx; out->dvy = L.dvy; out->dt = L.dt;
+        out->courant_x = L.courant_x; out->courant_vy = L.courant_vy;
+        out->cells = L.cells; out->tile_rows = L.ti; out->tile_planes = L.kc;
+        out->block = L.block; out->n_tiles = L.nwg; out->bytes_device = L.bytes_device;
+    }
+    return FK_OK;
+}
+
+extern "C" int fk_saturation_check(const fk_state* tr, size_t n, double window_s, double rtol, int* out)
+{
+    if (!out || (!tr && n) || !(window_s > 0) || !(rtol >= 0)) return set_error(nullptr, FK_E_INVALID, "bad arguments to fk_saturation_check");
+    *out = 0;
+    if (n < 2) return FK_OK;
+    const fk_state& last = tr[n - 1];
+    // newest record at least one window older than the last one
+    long ref = -1;
+    for (long m = (long)n - 2; m >= 0; --m)
+        if (tr[m].t <= last.t - window_s * (1.0 - 1e-12)) { ref = m; break; }
+    if (ref < 0) return FK_OK;
+    const fk_state& a = tr[ref];
+    if (!(last.g_pe > 0)) return FK_OK;   // no electrons at the wall yet
+    const double qa[3] = {a.sigma + a.sigma_lo, a.g_pe, a.g_see};
+    const double qb[3] = {last.sigma + last.sigma_lo, last.g_pe, last.g_see};
+    for (int q = 0; q < 3; ++q)
+        if (!(std::fabs(qb[q] - qa[q]) <= rtol * std::fabs(qb[q]))) return FK_OK;
+    *out = 1;
+    return FK_OK;
+}
+

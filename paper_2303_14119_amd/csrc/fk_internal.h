@@ -1,0 +1,80 @@
+// fk_internal.h -- definitions shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "flashkin.h"
+
+namespace fk {
+
+// CODATA 2018 (the paper states no values)
+constexpr double kE = 1.602176634e-19;     // elementary charge, C
+constexpr double kMe = 9.1093837015e-31;   // electron mass, kg
+constexpr double kEps0 = 8.8541878128e-12; // vacuum permittivity, F/m
+constexpr double kPi = 3.14159265358979323846;
+
+constexpr uint32_t kFlagCfl = 1u;
+constexpr uint32_t kFlagNonfinite = 2u;
+
+constexpr int kFieldThreads = 1024;  // one workgroup runs the reduction/field kernel
+constexpr size_t kLdsBudget = 64 * 1024;
+
+// Scalars of the current state, in device memory, written only by the
+// reduction/field kernel (and by the host through fk_write_state).
+struct DevState {
+    int64_t step;
+    double sigma, sigma_lo;      // Neumaier pair: sigma^n = sigma + sigma_lo
+    double g_pe, g_see, g_top;   // fluxes of f^n (Eq 13-14)
+    double emitted;              // flux of the emission row built from g_see
+    double loss_v, n_total, resid;
+    double gscale;               // emission row = gscale * ghat
+    double courant_vx_max;       // largest |a_x| dt / dv_x seen
+    uint32_t flags;
+    uint32_t pad;
+};
+
+// Derived grid, step and launch shape of a parameter set (host side).
+struct Layout {
+    double dx, dvx, dvy, dt;
+    double courant_x, courant_vy;
+    double dy;                   // signed v_y Courant number a_y dt / dv_y
+    int64_t cells;
+    int elem;                    // bytes per f element
+    int block;                   // threads of the sweep workgroup (one per v_y column)
+    int ti;                      // v_x rows per tile
+    int kc;                      // x planes per tile
+    int n_it, n_kc, nwg;
+    size_t lds_sweep, lds_moments;
+    uint64_t bytes_device;
+};
+
+int derive_layout(const fk_params* p, Layout* L, std::string* why);
+int set_error(std::string* slot, int code, const std::string& msg);
+const char* global_error();
+
+// Block of device buffers of one instance (owned by a context or a batch).
+struct Buffers {
+    void* f[2];
+    double* delta;    // [nvx][nvy]
+    double* ghat;     // [nvx][nvy]
+    double* fsrc64;   // [nvx][nvy], normalised, FP64
+    void* fsrc;       // [nvx][nvy], normalised, element type of f
+    double* wband;    // [nx]
+    double* srck;     // [nx], dt (J/e) w_k / (x_hi - x_lo) or 0
+    double* part_n;   // [nx][n_it]
+    double* part_wall;// [n_it][2]
+    double* part_top; // [n_it]
+    double* part_lv;  // [nwg]
+    double* ne;       // [nx]
+    double* ex;       // [nx]
+    double* dxk;      // [nx], v_x Courant number of each plane
+    double* consts;   // [4]: zsum, srcnorm, injected per step, emission prefactor
+    DevState* st;
+    fk_state* ring;   // [trace_cap]
+};
+
+}  // namespace fk

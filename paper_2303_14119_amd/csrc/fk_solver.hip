@@ -1,0 +1,739 @@
+// fk_solver.hip -- one simulation context: tables, time step, state I/O.
+//
+// Kernels per step: the fused sweep over all tiles of f (HBM-bound), then
+// the one-workgroup field kernel that reduces the new moments and prepares
+// the next step.  Steps are replayed from captured HIP graphs.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "fk_kernels.h"
+
+namespace fk {
+
+// ---------------------------------------------------------------- tables
+
+struct TableArgs {
+    double* delta;
+    double* ghat;
+    double* fsrc64;
+    double* wband;
+    double* srck;
+    double* consts;
+    void* fsrc;
+    int is_f32;
+    int nx, nvx, nvy;
+    double vmax_x, vmax_y, dvx, dvy, dx, dt;
+    double delta_max, a_max_ev, ks, t_se_ev, t_src_ev;
+    double j_src, x_lo, x_hi;
+    uint32_t mask;
+};
+
+// SEY of Eq 8-9 at incident energy a_ev (Eq 10) and angle alpha (Eq 11).
+__device__ double sey_yield(double delta_max, double a_max_ev, double ks, double a_ev, double alpha)
+{
+    const double z = 1.284 * a_ev / (a_max_ev * (1.0 + ks * alpha * alpha / kPi));
+    if (!(z > 0.0)) return 0.0;
+    const double rise = -expm1(-pow(z, 1.725));   // 1 - exp(-z^1.725)
+    return 1.526 * delta_max * (1.0 + ks * alpha * alpha / (2.0 * kPi)) * rise / pow(z, 0.725);
+}
+
+// Per velocity cell: SEY on v_x < 0, emission shape on v_x > 0, source VDF
+// on v_y > 0 (unnormalised).
+__global__ void k_tables_cells(TableArgs a)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= a.nvx * a.nvy) return;
+    const int i = m / a.nvy, j = m % a.nvy;
+    const double vx = cell_v(i, a.nvx, a.dvx);
+    const double vy = cell_v(j, a.nvy, a.dvy);
+    const double v2 = vx * vx + vy * vy;
+    double dl = 0.0, g = 0.0, s = 0.0;
+    if (vx < 0.0) {
+        const double a_ev = 0.5 * kMe * v2 / kE;
+        const double alpha = atan(fabs(vy / vx));
+        dl = sey_yield(a.delta_max, a.a_max_ev, a.ks, a_ev, alpha);
+    }
+    if (vx > 0.0) g = exp(-kMe * v2 / (2.0 * a.t_se_ev * kE));
+    if (vy > 0.0) s = exp(-kMe * v2 / (2.0 * a.t_src_ev * kE));
+    a.delta[m] = dl;
+    a.ghat[m] = g;
+    a.fsrc64[m] = s;
+}
+
+// Normalisations (one workgroup): Z = sum v_x ghat dv^2, the source VDF
+// scaled to unit integral, the band weights and per-plane source
+// coefficients, and the particles injected per step.
+__global__ void __launch_bounds__(kFieldThreads) k_tables_norm(TableArgs a)
+{
+    __shared__ double sh[kFieldThreads];
+    const int t = threadIdx.x, T = blockDim.x;
+    const int nv = a.nvx * a.nvy;
+    const double dv2 = a.dvx * a.dvy;
+    double z = 0.0, s = 0.0;
+    for (int m = t; m < nv; m += T) {
+        const int i = m / a.nvy;
+        const double vx = cell_v(i, a.nvx, a.dvx);
+        if (vx > 0.0) z += vx * a.ghat[m] * dv2;
+        s += a.fsrc64[m] * dv2;
+    }
+    z = block_sum(z, sh);
+    s = block_sum(s, sh);
+    double norm = 0.0;
+    for (int m = t; m < nv; m += T) {
+        const double v = s > 0.0 ? a.fsrc64[m] / s : 0.0;
+        a.fsrc64[m] = v;
+        if (a.is_f32) static_cast<float*>(a.fsrc)[m] = (float)v;
+        else static_cast<double*>(a.fsrc)[m] = v;
+        norm += v * dv2;
+    }
+    norm = block_sum(norm, sh);
+    const double band = a.x_hi - a.x_lo;
+    double inj = 0.0;
+    for (int k = t; k < a.nx; k += T) {
+        const double lo = fmax(k * a.dx, a.x_lo), hi = fmin((k + 1) * a.dx, a.x_hi);
+        const double w = hi > lo ? (hi - lo) / a.dx : 0.0;
+        a.wband[k] = w;
+        const double c = (band > 0.0 && (a.mask & FK_PHYS_SRC)) ? a.dt * (a.j_src / kE) * w / band : 0.0;
+        a.srck[k] = c;
+        inj += c * a.dx;
+    }
+    inj = block_sum(inj, sh);
+    if (t == 0) {
+        a.consts[0] = z;
+        a.consts[1] = norm;
+        a.consts[2] = inj * norm;
+        const double mt = kMe / (a.t_se_ev * kE);
+        a.consts[3] = pow(mt, 1.5) / sqrt(2.0 * kPi);   // Eq 15 prefactor per unit Gamma_see
+    }
+}
+
+// ---------------------------------------------------------------- kernels
+
+template <typename T, int TI, int MAXB>
+__global__ void __launch_bounds__(MAXB) k_sweep(SweepArgs<T> a)
+{
+    extern __shared__ double smem[];
+    sweep_tile<T, TI>(a, xcd_remap(blockIdx.x, gridDim.x), smem);
+}
+
+template <typename T, int TI>
+__global__ void __launch_bounds__(1024) k_moments(SweepArgs<T> a)
+{
+    extern __shared__ double smem[];
+    moments_tile<T, TI>(a, blockIdx.x, smem);
+}
+
+__global__ void __launch_bounds__(kFieldThreads) k_field(FieldArgs a)
+{
+    __shared__ double sh[2 * kFieldThreads];
+    field_block(a, sh);
+}
+
+}  // namespace fk
+
+using namespace fk;
+
+// ---------------------------------------------------------------- context
+
+struct fk_ctx {
+    fk_params p;
+    Layout L;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    bool own_f = true;
+    Buffers b{};
+    void* pool = nullptr;         // small buffers
+    int cur = 0;                  // which f buffer holds the state
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    int graph_steps = 0;          // steps per graph launch (even)
+    bool graph_ready = false;
+    int sticky = FK_OK;
+    std::string err;
+    // trace
+    std::vector<fk_state> history;
+    int64_t drained_step = -1;    // last step whose record has been drained
+    // profiling
+    bool prof = false;
+    struct Ev { hipEvent_t a, b, c; };   // sweep a->b, field b->c
+    std::vector<Ev> events;
+    std::vector<hipEvent_t> spare;
+};
+
+namespace {
+
+int hip_fail(fk_ctx* c, hipError_t e, const char* what)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return set_error(c ? &c->err : nullptr, FK_E_HIP, m);
+}
+
+#define FK_HIP(c, call)                                        \
+    do {                                                       \
+        hipError_t e_ = (call);                                \
+        if (e_ != hipSuccess) return hip_fail((c), e_, #call); \
+    } while (0)
+
+template <typename T>
+SweepArgs<T> sweep_args(const fk_ctx* c, int from)
+{
+    SweepArgs<T> a{};
+    a.fin = static_cast<const T*>(c->b.f[from]);
+    a.fout = static_cast<T*>(c->b.f[from ^ 1]);
+    a.dxk = c->b.dxk;
+    a.srck = c->b.srck;
+    a.fsrc = static_cast<const T*>(c->b.fsrc);
+    a.ghat = c->b.ghat;
+    a.delta = c->b.delta;
+    a.st = c->b.st;
+    a.part_n = c->b.part_n;
+    a.part_wall = c->b.part_wall;
+    a.part_top = c->b.part_top;
+    a.part_lv = c->b.part_lv;
+    a.nx = c->p.nx;
+    a.nvx = c->p.nvx;
+    a.nvy = c->p.nvy;
+    a.n_it = c->L.n_it;
+    a.kc = c->L.kc;
+    a.dvx = c->L.dvx;
+    a.dt_dx = c->L.dt / c->L.dx;
+    a.dy = c->L.dy;
+    a.x_on = (c->p.physics_mask & FK_PHYS_X) ? 1 : 0;
+    a.tile_base = 0;
+    a.nwg_total = c->L.nwg;
+    return a;
+}
+
+template <typename T, int TI, int MAXB>
+void launch_sweep_t(const fk_ctx* c, int from, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_sweep<T, TI, MAXB>), dim3(c->L.nwg), dim3(c->L.block), c->L.lds_sweep, s,
+                       sweep_args<T>(c, from));
+}
+
+void launch_sweep(const fk_ctx* c, int from, hipStream_t s)
+{
+    const bool small = c->L.block <= 512;
+    if (c->L.elem == 4) {
+        switch (c->L.ti) {
+        case 16: launch_sweep_t<float, 16, 512>(c, from, s); break;
+        case 8: small ? launch_sweep_t<float, 8, 512>(c, from, s) : launch_sweep_t<float, 8, 1024>(c, from, s); break;
+        default: launch_sweep_t<float, 4, 1024>(c, from, s); break;
+        }
+    } else {
+        switch (c->L.ti) {
+        case 8: launch_sweep_t<double, 8, 512>(c, from, s); break;
+        default: launch_sweep_t<double, 4, 1024>(c, from, s); break;
+        }
+    }
+}
+
+void launch_moments(const fk_ctx* c, hipStream_t s)
+{
+    if (c->L.elem == 4) {
+        auto a = sweep_args<float>(c, c->cur);
+        switch (c->L.ti) {
+        case 16: hipLaunchKernelGGL((k_moments<float, 16>), dim3(c->L.nwg), dim3(c->L.block), c->L.lds_moments, s, a); break;
+        case 8: hipLaunchKernelGGL((k_moments<float, 8>), dim3(c->L.nwg), dim3(c->L.block), c->L.lds_moments, s, a); break;
+        default: hipLaunchKernelGGL((k_moments<float, 4>), dim3(c->L.nwg), dim3(c->L.block), c->L.lds_moments, s, a); break;
+        }
+    } else {
+        auto a = sweep_args<double>(c, c->cur);
+        switch (c->L.ti) {
+        case 8: hipLaunchKernelGGL((k_moments<double, 8>), dim3(c->L.nwg), dim3(c->L.block), c->L.lds_moments, s, a); break;
+        default: hipLaunchKernelGGL((k_moments<double, 4>), dim3(c->L.nwg), dim3(c->L.block), c->L.lds_moments, s, a); break;
+        }
+    }
+}
+
+FieldArgs field_args(const fk_ctx* c, int advance)
+{
+    FieldArgs a{};
+    a.part_n = c->b.part_n;
+    a.part_wall = c->b.part_wall;
+    a.part_top = c->b.part_top;
+    a.part_lv = c->b.part_lv;
+    a.consts = c->b.consts;
+    a.ne = c->b.ne;
+    a.ex = c->b.ex;
+    a.dxk = c->b.dxk;
+    a.st = c->b.st;
+    a.ring = c->b.ring;
+    a.nx = c->p.nx;
+    a.n_it = c->L.n_it;
+    a.nwg = c->L.nwg;
+    a.advance = advance;
+    a.mask = c->p.physics_mask;
+    a.emission_norm = c->p.emission_norm;
+    a.trace_stride = c->p.trace_stride;
+    a.trace_cap = c->p.trace_cap;
+    a.dx = c->L.dx;
+    a.dv2 = c->L.dvx * c->L.dvy;
+    a.dt = c->L.dt;
+    a.dvx = c->L.dvx;
+    a.ex_ext = c->p.ex_external;
+    return a;
+}
+
+void launch_field(const fk_ctx* c, int advance, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_field, dim3(1), dim3(kFieldThreads), 0, s, field_args(c, advance));
+}
+
+// one step from buffer `from` into the other
+void enqueue_step(const fk_ctx* c, int from, hipStream_t s)
+{
+    launch_sweep(c, from, s);
+    launch_field(c, 1, s);
+}
+
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+int alloc_buffers(fk_ctx* c, void* fa, void* fb)
+{
+    const fk_params& p = c->p;
+    const Layout& L = c->L;
+    const size_t v2 = (size_t)p.nvx * p.nvy;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+    const size_t o_delta = take(v2 * 8), o_ghat = take(v2 * 8), o_fsrc64 = take(v2 * 8),
+                 o_fsrc = take(v2 * L.elem), o_wband = take(p.nx * 8), o_srck = take(p.nx * 8),
+                 o_pn = take((size_t)p.nx * L.n_it * 8), o_pw = take((size_t)L.n_it * 16),
+                 o_pt = take((size_t)L.n_it * 8), o_plv = take((size_t)L.nwg * 8),
+                 o_ne = take(p.nx * 8), o_ex = take(p.nx * 8), o_dxk = take(p.nx * 8),
+                 o_consts = take(64), o_st = take(sizeof(DevState)),
+                 o_ring = take((size_t)p.trace_cap * sizeof(fk_state));
+    if (hipMalloc(&c->pool, off) != hipSuccess) {
+        c->pool = nullptr;
+        return set_error(&c->err, FK_E_OOM, "device allocation of tables and partials failed");
+    }
+    char* base = static_cast<char*>(c->pool);
+    c->b.delta = (double*)(base + o_delta);
+    c->b.ghat = (double*)(base + o_ghat);
+    c->b.fsrc64 = (double*)(base + o_fsrc64);
+    c->b.fsrc = base + o_fsrc;
+    c->b.wband = (double*)(base + o_wband);
+    c->b.srck = (double*)(base + o_srck);
+    c->b.part_n = (double*)(base + o_pn);
+    c->b.part_wall = (double*)(base + o_pw);
+    c->b.part_top = (double*)(base + o_pt);
+    c->b.part_lv = (double*)(base + o_plv);
+    c->b.ne = (double*)(base + o_ne);
+    c->b.ex = (double*)(base + o_ex);
+    c->b.dxk = (double*)(base + o_dxk);
+    c->b.consts = (double*)(base + o_consts);
+    c->b.st = (DevState*)(base + o_st);
+    c->b.ring = (fk_state*)(base + o_ring);
+    FK_HIP(c, hipMemsetAsync(c->pool, 0, off, c->stream));
+    const size_t fbytes = (size_t)L.cells * L.elem;
+    if (fa) {
+        c->own_f = false;
+        c->b.f[0] = fa;
+        c->b.f[1] = fb;
+    } else {
+        c->own_f = true;
+        if (hipMalloc(&c->b.f[0], fbytes) != hipSuccess) {
+            c->b.f[0] = nullptr;
+            return set_error(&c->err, FK_E_OOM, "device allocation of f failed");
+        }
+        if (hipMalloc(&c->b.f[1], fbytes) != hipSuccess) {
+            c->b.f[1] = nullptr;
+            return set_error(&c->err, FK_E_OOM, "device allocation of f failed");
+        }
+    }
+    FK_HIP(c, hipMemsetAsync(c->b.f[0], 0, fbytes, c->stream));
+    FK_HIP(c, hipMemsetAsync(c->b.f[1], 0, fbytes, c->stream));
+    return FK_OK;
+}
+
+int build_tables(fk_ctx* c)
+{
+    const fk_params& p = c->p;
+    TableArgs a{};
+    a.delta = c->b.delta;
+    a.ghat = c->b.ghat;
+    a.fsrc64 = c->b.fsrc64;
+    a.wband = c->b.wband;
+    a.srck = c->b.srck;
+    a.consts = c->b.consts;
+    a.fsrc = c->b.fsrc;
+    a.is_f32 = c->L.elem == 4;
+    a.nx = p.nx;
+    a.nvx = p.nvx;
+    a.nvy = p.nvy;
+    a.vmax_x = p.vmax_x;
+    a.vmax_y = p.vmax_y;
+    a.dvx = c->L.dvx;
+    a.dvy = c->L.dvy;
+    a.dx = c->L.dx;
+    a.dt = c->L.dt;
+    a.delta_max = p.delta_max;
+    a.a_max_ev = p.a_max_ev;
+    a.ks = p.ks;
+    a.t_se_ev = p.t_se_ev;
+    a.t_src_ev = p.t_src_ev;
+    a.j_src = p.j_src;
+    a.x_lo = p.x_src_lo;
+    a.x_hi = p.x_src_hi;
+    a.mask = p.physics_mask;
+    const int nv = p.nvx * p.nvy;
+    hipLaunchKernelGGL(k_tables_cells, dim3((nv + 255) / 256), dim3(256), 0, c->stream, a);
+    hipLaunchKernelGGL(k_tables_norm, dim3(1), dim3(kFieldThreads), 0, c->stream, a);
+    FK_HIP(c, hipGetLastError());
+    return FK_OK;
+}
+
+// recompute the prologue quantities of the current f and state
+int refresh(fk_ctx* c)
+{
+    launch_moments(c, c->stream);
+    launch_field(c, 0, c->stream);
+    FK_HIP(c, hipGetLastError());
+    return FK_OK;
+}
+
+int capture_graphs(fk_ctx* c)
+{
+    c->graph_steps = 16;
+    for (int start = 0; start < 2; ++start) {
+        hipGraph_t g = nullptr;
+        FK_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+        for (int s = 0; s < c->graph_steps; ++s) enqueue_step(c, (start + s) & 1, c->cap_stream);
+        hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+        if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&c->graph[start], g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+    }
+    c->graph_ready = true;
+    return FK_OK;
+}
+
+hipEvent_t get_event(fk_ctx* c)
+{
+    if (!c->spare.empty()) {
+        hipEvent_t e = c->spare.back();
+        c->spare.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+int read_devstate(fk_ctx* c, DevState* out)
+{
+    FK_HIP(c, hipMemcpyAsync(out, c->b.st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
+    FK_HIP(c, hipStreamSynchronize(c->stream));
+    return FK_OK;
+}
+
+int flags_to_code(uint32_t f)
+{
+    if (f & kFlagNonfinite) return FK_E_NONFINITE;
+    if (f & kFlagCfl) return FK_E_CFL;
+    return FK_OK;
+}
+
+int drain(fk_ctx* c, size_t* fresh_begin)
+{
+    DevState s;
+    int rc = read_devstate(c, &s);
+    if (rc) return rc;
+    *fresh_begin = c->history.size();
+    const int64_t stride = c->p.trace_stride, cap = c->p.trace_cap;
+    const int64_t last_rec = s.step / stride;               // index of the newest record
+    int64_t first_rec = c->drained_step < 0 ? 0 : c->drained_step / stride + 1;
+    int code = FK_OK;
+    if (last_rec - first_rec + 1 > cap) {
+        first_rec = last_rec - cap + 1;
+        code = FK_E_STATE;
+    }
+    const int64_t n = last_rec - first_rec + 1;
+    if (n > 0) {
+        std::vector<fk_state> tmp((size_t)cap);
+        FK_HIP(c, hipMemcpyAsync(tmp.data(), c->b.ring, sizeof(fk_state) * cap, hipMemcpyDeviceToHost, c->stream));
+        FK_HIP(c, hipStreamSynchronize(c->stream));
+        for (int64_t r = first_rec; r <= last_rec; ++r) c->history.push_back(tmp[(size_t)(r % cap)]);
+        c->drained_step = last_rec * stride;
+    }
+    if (code) set_error(&c->err, code, "trace ring overflowed; older records were lost");
+    return code;
+}
+
+void release(fk_ctx* c)
+{
+    if (!c) return;
+    if (c->stream || c->pool) (void)hipStreamSynchronize(c->stream);
+    for (auto& g : c->graph)
+        if (g) (void)hipGraphExecDestroy(g);
+    for (auto& e : c->events) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+        (void)hipEventDestroy(e.c);
+    }
+    for (auto e : c->spare) (void)hipEventDestroy(e);
+    if (c->own_f) {
+        if (c->b.f[0]) (void)hipFree(c->b.f[0]);
+        if (c->b.f[1]) (void)hipFree(c->b.f[1]);
+    }
+    if (c->pool) (void)hipFree(c->pool);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    delete c;
+}
+
+int create_impl(const fk_params* p, void* stream, void* fa, void* fb, fk_ctx** out)
+{
+    if (!out) return set_error(nullptr, FK_E_INVALID, "out is NULL");
+    *out = nullptr;
+    Layout L;
+    std::string why;
+    int rc = derive_layout(p, &L, &why);
+    if (rc) return set_error(nullptr, rc, why);
+    if ((fa == nullptr) != (fb == nullptr)) return set_error(nullptr, FK_E_INVALID, "borrowed buffers: give both or neither");
+    if (fa && fa == fb) return set_error(nullptr, FK_E_INVALID, "borrowed buffers must differ");
+    fk_ctx* c = new (std::nothrow) fk_ctx();
+    if (!c) return set_error(nullptr, FK_E_OOM, "host allocation failed");
+    c->p = *p;
+    c->L = L;
+    c->stream = static_cast<hipStream_t>(stream);
+    hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        std::string m = std::string("HIP initialisation failed: ") + hipGetErrorString(e);
+        release(c);
+        return set_error(nullptr, FK_E_HIP, m);
+    }
+    rc = alloc_buffers(c, fa, fb);
+    if (!rc) rc = build_tables(c);
+    if (!rc) rc = refresh(c);
+    if (!rc) rc = capture_graphs(c);
+    if (!rc) {
+        e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) rc = hip_fail(c, e, "create");
+    }
+    if (rc) {
+        std::string m = c->err;
+        release(c);
+        return set_error(nullptr, rc, m);
+    }
+    *out = c;
+    return FK_OK;
+}
+
+}  // namespace
+
+extern "C" const char* fk_last_error(const fk_ctx* c) { return c ? c->err.c_str() : global_error(); }
+
+extern "C" int fk_create(const fk_params* p, void* stream, fk_ctx** out)
+{
+    return create_impl(p, stream, nullptr, nullptr, out);
+}
+
+extern "C" int fk_create_borrowed(const fk_params* p, void* stream, void* f_a, void* f_b, fk_ctx** out)
+{
+    if (!f_a || !f_b) return set_error(nullptr, FK_E_INVALID, "borrowed buffers must not be NULL");
+    return create_impl(p, stream, f_a, f_b, out);
+}
+
+extern "C" int fk_destroy(fk_ctx* c)
+{
+    if (!c) return FK_E_INVALID;
+    release(c);
+    return FK_OK;
+}
+
+extern "C" int fk_query(const fk_ctx* c, fk_info* out)
+{
+    if (!c || !out) return FK_E_INVALID;
+    out->dx = c->L.dx; out->dvx = c->L.dvx; out->dvy = c->L.dvy; out->dt = c->L.dt;
+    out->courant_x = c->L.courant_x; out->courant_vy = c->L.courant_vy;
+    out->cells = c->L.cells; out->tile_rows = c->L.ti; out->tile_planes = c->L.kc;
+    out->block = c->L.block; out->n_tiles = c->L.nwg; out->bytes_device = c->L.bytes_device;
+    return FK_OK;
+}
+
+extern "C" int fk_step(fk_ctx* c, int64_t n)
+{
+    if (!c || n < 0) return set_error(c ? &c->err : nullptr, FK_E_INVALID, "bad arguments to fk_step");
+    if (c->sticky) return c->sticky;
+    if (c->prof) {
+        for (int64_t s = 0; s < n; ++s) {
+            hipEvent_t e0 = get_event(c), e1 = get_event(c), e2 = get_event(c);
+            if (!e0 || !e1 || !e2) return set_error(&c->err, FK_E_HIP, "hipEventCreate failed");
+            FK_HIP(c, hipEventRecord(e0, c->stream));
+            launch_sweep(c, c->cur, c->stream);
+            FK_HIP(c, hipEventRecord(e1, c->stream));
+            launch_field(c, 1, c->stream);
+            FK_HIP(c, hipEventRecord(e2, c->stream));
+            c->events.push_back({e0, e1, e2});
+            c->cur ^= 1;
+        }
+        FK_HIP(c, hipGetLastError());
+        return FK_OK;
+    }
+    int64_t left = n;
+    if (c->graph_ready) {
+        while (left >= c->graph_steps) {
+            FK_HIP(c, hipGraphLaunch(c->graph[c->cur], c->stream));
+            left -= c->graph_steps;   // graph_steps is even: cur unchanged
+        }
+    }
+    for (; left > 0; --left) {
+        enqueue_step(c, c->cur, c->stream);
+        c->cur ^= 1;
+    }
+    FK_HIP(c, hipGetLastError());
+    return FK_OK;
+}
+
+extern "C" int fk_sync(fk_ctx* c)
+{
+    if (!c) return FK_E_INVALID;
+    DevState s;
+    int rc = read_devstate(c, &s);
+    if (rc) return rc;
+    int code = flags_to_code(s.flags);
+    if (code) {
+        c->sticky = code;
+        return set_error(&c->err, code, code == FK_E_CFL ? "v_x Courant number above one (E_x too strong for dt)"
+                                                          : "non-finite moment, flux or surface charge");
+    }
+    return FK_OK;
+}
+
+extern "C" int fk_read_f(fk_ctx* c, void* dst, size_t bytes, int on_device)
+{
+    if (!c || !dst) return FK_E_INVALID;
+    const size_t need = (size_t)c->L.cells * c->L.elem;
+    if (bytes < need) return set_error(&c->err, FK_E_INVALID, "destination too small");
+    FK_HIP(c, hipMemcpyAsync(dst, c->b.f[c->cur], need, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    FK_HIP(c, hipStreamSynchronize(c->stream));
+    return FK_OK;
+}
+
+extern "C" int fk_read_state(fk_ctx* c, fk_state* out)
+{
+    if (!c || !out) return FK_E_INVALID;
+    DevState s;
+    int rc = read_devstate(c, &s);
+    if (rc) return rc;
+    out->step = s.step;
+    out->t = (double)s.step * c->L.dt;
+    out->sigma = s.sigma;
+    out->sigma_lo = s.sigma_lo;
+    out->g_pe = s.g_pe;
+    out->g_see = s.g_see;
+    out->g_top = s.g_top;
+    out->emitted = s.emitted;
+    out->loss_v = s.loss_v;
+    out->n_total = s.n_total;
+    out->resid = s.resid;
+    return FK_OK;
+}
+
+extern "C" int fk_read_field(fk_ctx* c, double* ex, double* ne, int on_device)
+{
+    if (!c) return FK_E_INVALID;
+    const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (ex) FK_HIP(c, hipMemcpyAsync(ex, c->b.ex, c->p.nx * sizeof(double), k, c->stream));
+    if (ne) FK_HIP(c, hipMemcpyAsync(ne, c->b.ne, c->p.nx * sizeof(double), k, c->stream));
+    FK_HIP(c, hipStreamSynchronize(c->stream));
+    return FK_OK;
+}
+
+extern "C" int fk_read_tables(fk_ctx* c, double* delta, double* ghat, double* fsrc, double* wband)
+{
+    if (!c) return FK_E_INVALID;
+    const size_t v2 = (size_t)c->p.nvx * c->p.nvy * sizeof(double);
+    if (delta) FK_HIP(c, hipMemcpyAsync(delta, c->b.delta, v2, hipMemcpyDeviceToHost, c->stream));
+    if (ghat) FK_HIP(c, hipMemcpyAsync(ghat, c->b.ghat, v2, hipMemcpyDeviceToHost, c->stream));
+    if (fsrc) FK_HIP(c, hipMemcpyAsync(fsrc, c->b.fsrc64, v2, hipMemcpyDeviceToHost, c->stream));
+    if (wband) FK_HIP(c, hipMemcpyAsync(wband, c->b.wband, c->p.nx * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    FK_HIP(c, hipStreamSynchronize(c->stream));
+    return FK_OK;
+}
+
+extern "C" int fk_read_trace(fk_ctx* c, fk_state* dst, size_t cap, size_t* n_out)
+{
+    if (!c || !n_out || (!dst && cap)) return FK_E_INVALID;
+    size_t begin = 0;
+    int rc = drain(c, &begin);
+    if (rc && rc != FK_E_STATE) return rc;
+    size_t n = std::min(cap, c->history.size() - begin);
+    if (n) std::memcpy(dst, c->history.data() + begin, n * sizeof(fk_state));
+    *n_out = n;
+    return rc;
+}
+
+extern "C" int fk_write_state(fk_ctx* c, const void* f, int on_device, double sigma, double sigma_lo, int64_t step)
+{
+    if (!c || step < 0 || !std::isfinite(sigma) || !std::isfinite(sigma_lo)) return FK_E_INVALID;
+    FK_HIP(c, hipStreamSynchronize(c->stream));
+    if (f) {
+        const size_t need = (size_t)c->L.cells * c->L.elem;
+        FK_HIP(c, hipMemcpyAsync(c->b.f[c->cur], f, need, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+    }
+    DevState s{};
+    s.step = step;
+    s.sigma = sigma;
+    s.sigma_lo = sigma_lo;
+    FK_HIP(c, hipMemcpyAsync(c->b.st, &s, sizeof(s), hipMemcpyHostToDevice, c->stream));
+    int rc = refresh(c);
+    if (rc) return rc;
+    FK_HIP(c, hipStreamSynchronize(c->stream));
+    c->sticky = FK_OK;
+    c->history.clear();
+    c->drained_step = step - 1;
+    // the record of the restored state itself is drained from the ring only
+    // if it falls on the stride
+    if (step % c->p.trace_stride != 0) c->drained_step = step;
+    return FK_OK;
+}
+
+extern "C" int fk_saturated(fk_ctx* c, double window_s, double rtol, int* out)
+{
+    if (!c || !out) return FK_E_INVALID;
+    size_t begin = 0;
+    int rc = drain(c, &begin);
+    if (rc && rc != FK_E_STATE) return rc;
+    return fk_saturation_check(c->history.data(), c->history.size(), window_s, rtol, out);
+}
+
+extern "C" int fk_set_profiling(fk_ctx* c, int on)
+{
+    if (!c) return FK_E_INVALID;
+    FK_HIP(c, hipStreamSynchronize(c->stream));
+    for (auto& e : c->events) {
+        c->spare.push_back(e.a);
+        c->spare.push_back(e.b);
+        c->spare.push_back(e.c);
+    }
+    c->events.clear();
+    c->prof = on != 0;
+    return FK_OK;
+}
+
+extern "C" int fk_kernel_times(fk_ctx* c, double* sweep_ms, int64_t* sweep_n, double* field_ms, int64_t* field_n)
+{
+    if (!c) return FK_E_INVALID;
+    FK_HIP(c, hipStreamSynchronize(c->stream));
+    double t[2] = {0, 0};
+    int64_t n[2] = {0, 0};
+    for (auto& e : c->events) {
+        float ms = 0;
+        FK_HIP(c, hipEventElapsedTime(&ms, e.a, e.b));
+        t[0] += ms;
+        FK_HIP(c, hipEventElapsedTime(&ms, e.b, e.c));
+        t[1] += ms;
+        n[0] += 1;
+        n[1] += 1;
+    }
+    if (sweep_ms) *sweep_ms = t[0];
+    if (sweep_n) *sweep_n = n[0];
+    if (field_ms) *field_ms = t[1];
+    if (field_n) *field_n = n[1];
+    return FK_OK;
+}

@@ -29,7 +29,7 @@ def tiny(**kw):
 def centres(vmax, n):
     """Cell-centred grid on [-vmax, vmax] (the grid reading of the build)."""
     dv = 2 * vmax / n
-    return -vmax + (np.arange(n) + 0.5) * dv, dv
+    return (np.arange(n) + 0.5 - 0.5 * n) * dv, dv
 
 
 # ---------------------------------------------------------------- SEY, Eq 8-11
