@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Throughput of the 1D2V flashover step on one MI355X.
+
+Workload: 2048 (x) x 256 (v_x) x 256 (v_y) cells = 134,217,728 (1 mm, |E_y| =
+8 MV/m, delta_max = 2.2, A_max = 350 eV), FP32 f with FP64 sigma and fluxes.
+The state is first driven into the avalanche so the timed steps move real
+data; inputs are resident in HBM before the timed region starts.
+
+One step = the fused sweep kernel over all of f plus the reduction/field
+kernel (every part of the method).  ``value`` is cell-updates per second of
+the timed steps.  The roofline object prices the sweep kernel at its
+algorithmic traffic (read f once, write f once: 8 bytes per cell in FP32)
+against the MI355X HBM peak, with the kernel's launch durations measured by
+HIP events on the library's stream.  The CPU baseline is the FP64 oracle on a
+bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "sweep_c1_rocprof.md")
+
+
+def kernel_source_digest():
+    h = hashlib.sha256()
+    for name in ("fk_internal.h", "fk_kernels.h", "fk_sweep_fast.h", "fk_solver.hip"):
+        with open(os.path.join(ROOT, "paper_2303_14119_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per sweep launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    if not os.path.exists(PROFILE_SUMMARY):
+        return None
+    text = open(PROFILE_SUMMARY).read()
+    m_src = re.search(r"kernel_source_digest:\s*([0-9a-f]+)", text)
+    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_src or not m_b or m_src.group(1) != kernel_source_digest():
+        return None
+    return float(m_b.group(1))
+
+
+def cpu_baseline(cfg, budget_s=12.0):
+    """FP64 oracle on the host: whole steps of the same workload until about
+    budget_s seconds of CPU work have run."""
+    from oracle.solver import Oracle, get_threads, set_threads
+    threads = min(16, os.cpu_count() or 1)
+    set_threads(threads)
+    o = Oracle(cfg)
+    o.step(1)                       # first touch of the arrays
+    cells = cfg["nx"] * cfg["nvx"] * cfg["nvy"]
+    n, t0 = 0, time.perf_counter()
+    while True:
+        o.step(1)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    o.close()
+    return {"value": cells * n / el / 1e9, "unit": "Gcell-updates/s", "cores": get_threads(),
+            "kind": "oracle",
+            "sample": f"{n} whole FP64 steps of the same 2048x256x256 workload ({el:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--pre-steps", type=int, default=3000,
+                    help="steps run before the warmup to drive the state into the avalanche")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one plain 1 GiB device copy first (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU sharding is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2303_14119_amd import flashkin as fk
+    from paper_2303_14119_amd import workloads as W
+
+    cfg = W.c1()
+    dev = torch.device("cuda:0")
+    torch.cuda.init()
+    if args.calib_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    stream = torch.cuda.current_stream().cuda_stream
+    s = fk.Solver(cfg, "f32", stream=stream, trace_cap=64, trace_stride=1000)
+    cells = s.info["cells"]
+    # drive the state into the avalanche so the timed steps carry real data
+    s.step(args.pre_steps + args.warmup)
+    s.sync()
+    torch.cuda.synchronize()
+
+    # timed region: direct launches with a HIP event pair around every sweep
+    # launch on the library's stream (the live kernel timing)
+    s.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = s.kernel_times()
+    s.set_profiling(False)
+    s.sync()
+    # the same number of steps replayed from the captured HIP graphs, for
+    # reference (no per-kernel events there)
+    torch.cuda.synchronize()
+    g0 = time.perf_counter()
+    s.step(args.steps)
+    torch.cuda.synchronize()
+    g1 = time.perf_counter()
+    s.sync()
+    st = s.state()
+    s.close()
+
+    el = t1 - t0
+    ms_per_step = el * 1e3 / args.steps
+    value = cells * args.steps / el / 1e9
+    sweep_ms = kt["sweep_ms"] / max(kt["sweep_n"], 1)
+    field_ms = kt["field_ms"] / max(kt["field_n"], 1)
+    bytes_per_launch = 8.0 * cells
+    achieved = bytes_per_launch / (sweep_ms * 1e-3) / 1e9
+    traffic = measured_traffic()
+    out = {
+        "metric": "Gcell-updates/s",
+        "value": round(value, 3),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "plain single run, 2048x256x256 cells over 1 mm, |E_y| 8 MV/m, "
+                               "delta_max 2.2, A_max 350 eV, FP32 f, FP64 sigma and fluxes",
+                   "nx": cfg["nx"], "nvx": cfg["nvx"], "nvy": cfg["nvy"], "cells": cells,
+                   "dt_s": s.dt, "step_start": st["step"] - 2 * args.steps,
+                   "sigma_at_end": st["sigma"] + st["sigma_lo"],
+                   "graph_replay_value": round(cells * args.steps / (g1 - g0) / 1e9, 3)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "kernel": "k_sweep (fused x/v_x/v_y upwind + source + moments)",
+                     "kernel_ms": round(sweep_ms, 5), "reduce_field_interval_ms": round(field_ms, 5),
+                     "algorithmic_bytes_per_launch": bytes_per_launch},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

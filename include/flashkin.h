@@ -201,10 +201,11 @@ int fk_saturated(fk_ctx* ctx, double window_s, double rtol, int* out);
 int fk_saturation_check(const fk_state* trace, size_t n, double window_s, double rtol, int* out);
 
 /* Kernel timing.  While profiling is on, fk_step launches without graphs
- * and brackets every launch with HIP events on the context's stream;
- * fk_kernel_times synchronises and returns the summed milliseconds and the
- * launch counts of the sweep kernel and of the reduction/field kernel since
- * profiling was switched on. */
+ * and records a HIP event on the context's stream before and after every
+ * sweep launch; fk_kernel_times synchronises and returns the summed
+ * milliseconds and counts of the sweep launches and of the intervals from
+ * one sweep's end to the next sweep's start (the reduction and field
+ * kernels) since profiling was switched on. */
 int fk_set_profiling(fk_ctx* ctx, int on);
 int fk_kernel_times(fk_ctx* ctx, double* sweep_ms, int64_t* sweep_count, double* field_ms,
                     int64_t* field_count);

@@ -51,6 +51,9 @@ int derive_layout(const fk_params* p, Layout* L, std::string* why)
 
     const int64_t cells = (int64_t)p->nx * p->nvx * p->nvy;
     if (cells > ((int64_t)1 << 40)) return bad("grid too large");
+    // one x plane is addressed through a buffer descriptor with 32-bit offsets
+    if ((int64_t)p->nvx * p->nvy * (p->dtype == FK_F32 ? 4 : 8) > ((int64_t)1 << 30))
+        return bad("one x plane (nvx * nvy elements) must be at most 1 GiB");
 
     Layout l{};
     l.cells = cells;
@@ -80,8 +83,8 @@ int derive_layout(const fk_params* p, Layout* L, std::string* why)
     l.block = ((p->nvy + 63) / 64) * 64;
     int ti = p->tile_rows;
     if (ti == 0) {
-        if (l.elem == 4) ti = l.block <= 512 ? 16 : 8;
-        else ti = l.block <= 512 ? 8 : 4;
+        // 8 rows keep the fast FP32 body at four waves per SIMD; FP64 needs 4
+        ti = l.elem == 4 ? 8 : 4;
         while (ti > 4 && sweep_lds(ti, l.block, 128, l.elem) > kLdsBudget) ti /= 2;
     }
     if (ti == 16 && (l.elem != 4 || l.block > 512)) return bad("tile_rows 16 needs FK_F32 and nvy <= 512");
@@ -92,16 +95,19 @@ int derive_layout(const fk_params* p, Layout* L, std::string* why)
     if (kc == 0) {
         // enough workgroups to fill 256 compute units several times over,
         // but long enough x runs that the halo planes stay a small overhead
-        const int target = 2048;
+        const int target = 1024;
         int nkc = (target + l.n_it - 1) / l.n_it;
         kc = (p->nx + nkc - 1) / nkc;
-        if (kc < 4) kc = 4;
+        if (kc < 16) kc = 16;
         if (kc > 128) kc = 128;
     }
     if (kc > p->nx) kc = p->nx;
     l.kc = kc;
     l.n_kc = (p->nx + kc - 1) / kc;
     l.nwg = l.n_it * l.n_kc;
+    l.n_fast = 0;
+    for (int it = 0; it < l.n_it; ++it) l.n_fast += tile_is_fast(it, ti, p->nvx) ? 1 : 0;
+    l.n_generic = l.n_it - l.n_fast;
     l.lds_sweep = sweep_lds(ti, l.block, kc, l.elem);
     l.lds_moments = (size_t)kc * (l.block / 64) * 8 + (size_t)(l.block / 64) * 4 * 8;
     if (l.lds_sweep > kLdsBudget) return bad("tile needs more LDS than a workgroup has; lower tile_rows or tile_planes");

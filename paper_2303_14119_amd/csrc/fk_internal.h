@@ -48,11 +48,31 @@ struct Layout {
     int ti;                      // v_x rows per tile
     int kc;                      // x planes per tile
     int n_it, n_kc, nwg;
+    int n_fast, n_generic;       // v_x tiles taking the fast / generic sweep body
     size_t lds_sweep, lds_moments;
     uint64_t bytes_device;
 };
 
 int derive_layout(const fk_params* p, Layout* L, std::string* why);
+
+// Number of rows among r = 0..ti+1 of v_x tile `it` (rows i = it*ti - 1 + r)
+// with v_x <= 0, i.e. 2 i + 1 <= nvx: the split point of the fast sweep body.
+__host__ __device__ inline int tile_split(int it, int ti, int nvx)
+{
+    int s = 0;
+    for (int r = 0; r < ti + 2; ++r)
+        if (2 * (it * ti - 1 + r) + 1 <= nvx) ++s;
+    return s;
+}
+
+// Whether tile `it` takes the fast body: full (not ragged) and split at
+// 0, 1, ti+1 or ti+2.
+__host__ __device__ inline bool tile_is_fast(int it, int ti, int nvx)
+{
+    if ((it + 1) * ti > nvx) return false;
+    const int s = tile_split(it, ti, nvx);
+    return s == 0 || s == 1 || s == ti + 1 || s == ti + 2;
+}
 int set_error(std::string* slot, int code, const std::string& msg);
 const char* global_error();
 
@@ -65,14 +85,17 @@ struct Buffers {
     void* fsrc;       // [nvx][nvy], normalised, element type of f
     double* wband;    // [nx]
     double* srck;     // [nx], dt (J/e) w_k / (x_hi - x_lo) or 0
-    double* part_n;   // [nx][n_it]
+    double* part_n;   // [n_it][nx]  plane sums of each v_x tile
     double* part_wall;// [n_it][2]
     double* part_top; // [n_it]
     double* part_lv;  // [nwg]
+    double* plane_sum;// [nx]   plane sums reduced over the v_x tiles
+    double* wall_sum; // [4]    wall primary, wall secondary, top, velocity-box outflow
     double* ne;       // [nx]
     double* ex;       // [nx]
     double* dxk;      // [nx], v_x Courant number of each plane
     double* consts;   // [4]: zsum, srcnorm, injected per step, emission prefactor
+    int* tiles;       // [n_it]: fast v_x tiles, then generic ones
     DevState* st;
     fk_state* ring;   // [trace_cap]
 };

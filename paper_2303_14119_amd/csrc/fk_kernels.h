@@ -82,7 +82,7 @@ struct SweepArgs {
     const double* __restrict__ ghat;    // [nvx][nvy] emission shape
     const double* __restrict__ delta;   // [nvx][nvy] SEY
     const DevState* __restrict__ st;    // gscale of this step
-    double* __restrict__ part_n;        // [nx][n_it]
+    double* __restrict__ part_n;        // [n_it][nx] plane sums of each v_x tile
     double* __restrict__ part_wall;     // [n_it][2]
     double* __restrict__ part_top;      // [n_it]
     double* __restrict__ part_lv;       // [nwg]
@@ -90,23 +90,73 @@ struct SweepArgs {
     double dvx, dt_dx;                  // v_x of row i is cell_v(i, nvx, dvx)
     double dy;                          // signed v_y Courant number
     int x_on;
-    int tile_base, nwg_total;           // batched launches: first tile of the instance, grid size
+    const int* __restrict__ tile_list;  // v_x tile indices handled by this launch
+    int n_list;
 };
+
+// Reduction of the tile partials over the v_x tiles, fixed order: one
+// thread per x plane (coalesced over consecutive planes); workgroup 0 also
+// reduces the wall, top and velocity-box partials.
+struct ReduceArgs {
+    const double* __restrict__ part_n;      // [n_it][nx]
+    const double* __restrict__ part_wall;   // [n_it][2]
+    const double* __restrict__ part_top;    // [n_it]
+    const double* __restrict__ part_lv;     // [nwg]
+    double* __restrict__ plane_sum;         // [nx]
+    double* __restrict__ wall_sum;          // [4]: primary, secondary, top, velocity-box outflow
+    int nx, n_it, nwg;
+};
+
+// Buffer-resource access (CDNA raw buffer instructions).  A descriptor
+// covers one x plane; the row offset is a scalar, the column a 32-bit lane
+// offset.  Accesses at or beyond the descriptor's byte range read 0 and
+// drop stores (the hardware range check), which is how rows outside the
+// grid (null descriptor, range 0) and idle lanes (lane offset past the
+// plane) are masked without branches.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;
+constexpr int kIdleLaneOffset = 0x7ffffff0;
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, kRsrcWord3);
+}
+
+template <typename T> __device__ __forceinline__ T bload(rsrc_t r, int voff, int soff);
+template <> __device__ __forceinline__ float bload<float>(rsrc_t r, int voff, int soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <> __device__ __forceinline__ double bload<double>(rsrc_t r, int voff, int soff)
+{
+    typedef int v2i __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <typename T> __device__ __forceinline__ void bstore(T v, rsrc_t r, int voff, int soff);
+template <> __device__ __forceinline__ void bstore<float>(float v, rsrc_t r, int voff, int soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), r, voff, soff, 0);
+}
+template <> __device__ __forceinline__ void bstore<double>(double v, rsrc_t r, int voff, int soff)
+{
+    typedef int v2i __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i, v), r, voff, soff, 0);
+}
 
 // One workgroup owns v_x rows [i0, i0+TI) for all v_y columns (one thread per
 // column) and marches over x planes [k0, k0+kc).  Each thread keeps three x
-// planes of its rows (plus one halo row on each side) in registers:
+// planes of its rows (plus one halo row on each side) in registers and
+// prefetches the fourth:
 //   x sweep     upwind on sign(v_x) -- the plane below or above, in registers;
 //   v_x sweep   upwind on sign(a_x) -- the neighbouring row, in registers;
 //   v_y sweep   upwind on sign(a_y) -- the neighbouring column, through LDS;
 //   source      added on the planes overlapping the band.
-// f is read once and written once per cell (plus halo re-reads that mostly
-// hit L2).
-template <typename T, int TI>
-__device__ __forceinline__ void sweep_tile(const SweepArgs<T>& a, int wg, double* smem)
+// f is read once and written once per cell, plus the two halo rows (mostly
+// L2 hits: the neighbouring tiles run on the same XCD) and one halo plane per
+// chunk.
+template <typename T, int TI, bool EDGE>
+__device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, int wg, int it, int kci, double* smem)
 {
-    const int it = wg % a.n_it;
-    const int kci = wg / a.n_it;
     const int i0 = it * TI;
     const int k0 = kci * a.kc;
     const int k1 = min(k0 + a.kc, a.nx);
@@ -117,6 +167,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T>& a, int wg, double
     const bool jok = j < a.nvy;
     const int W = B + 2;
     const size_t plane = (size_t)a.nvx * a.nvy;
+    const uint32_t pbytes = (uint32_t)(plane * sizeof(T));
+    const int rowbytes = a.nvy * (int)sizeof(T);
 
     T* xb = reinterpret_cast<T*>(smem);                       // [2][TI][W]
     double* wsum = reinterpret_cast<double*>(xb + 2 * TI * W); // [kc][nw]
@@ -127,57 +179,78 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T>& a, int wg, double
         xb[m * W + W - 1] = T(0);
     }
 
-    bool ok[TI + 2];
-    T c[TI + 2];
+    // per-row data: row inside the grid (uniform), the lane's byte offset in
+    // a plane (out of range for rows outside the grid and idle lanes, so
+    // those read 0 and store nothing), and the signed x Courant number
+    // The sign of v_x of row i is the sign of 2i + 1 - nvx (exact integer
+    // test, uniform); the x sweep uses the split coefficients
+    // cp = max(c, 0), cn = min(c, 0) so it needs no per-row lane masks.
+    bool rv[TI + 2];
+    int vo[TI + 2];
+    T cp[TI + 2], cn[TI + 2];
 #pragma unroll
     for (int r = 0; r < TI + 2; ++r) {
         const int i = i0 - 1 + r;
-        ok[r] = jok && i >= 0 && i < a.nvx;
-        const double v = cell_v(i, a.nvx, a.dvx);
-        c[r] = (a.x_on && ok[r]) ? T(v * a.dt_dx) : T(0);
+        rv[r] = EDGE ? (i >= 0 && i < a.nvx) : true;   // interior tiles: every row is in the grid
+        vo[r] = (rv[r] && jok) ? i * rowbytes + j * (int)sizeof(T) : kIdleLaneOffset;
+        const T c = (a.x_on && rv[r]) ? T(cell_v(i, a.nvx, a.dvx) * a.dt_dx) : T(0);
+        cp[r] = 2 * i + 1 > a.nvx ? c : T(0);
+        cn[r] = 2 * i + 1 < a.nvx ? c : T(0);
     }
+    auto up_row = [&](int r) { return a.x_on && 2 * (i0 - 1 + r) + 1 > a.nvx; };   // v_x > 0
+    auto down_row = [&](int r) { return a.x_on && 2 * (i0 - 1 + r) + 1 < a.nvx; }; // v_x < 0
+    auto plane_in = [&](int kk) { return make_rsrc(a.fin + (size_t)kk * plane, pbytes); };
+    auto plane_out = [&](int kk) { return make_rsrc(a.fout + (size_t)kk * plane, pbytes); };
 
-    T fm[TI + 2], fc[TI + 2], fp[TI + 2];
-    const T* __restrict__ fin = a.fin + j;
+    // Rolling window of x planes k-1, k, k+1 and the prefetched k+2.  The
+    // planes just outside [k0, k1) are read only by the rows whose upwind
+    // side they are: the plane below by rows with v_x > 0, the plane above
+    // by rows with v_x < 0.
+    T fm[TI + 2], fc[TI + 2], fp[TI + 2], fn[TI + 2];
     if (k0 == 0) {
         // below the dielectric: the emission row of this step (Eq 15)
         const double gs = a.st->gscale;
 #pragma unroll
         for (int r = 0; r < TI + 2; ++r) {
             const int i = i0 - 1 + r;
-            fm[r] = ok[r] ? T(gs * a.ghat[(size_t)i * a.nvy + j]) : T(0);
+            fm[r] = (rv[r] && up_row(r) && jok) ? T(gs * a.ghat[(size_t)i * a.nvy + j]) : T(0);
         }
     } else {
-        const T* p = fin + (size_t)(k0 - 1) * plane;
+        const rsrc_t pr = plane_in(k0 - 1);
 #pragma unroll
-        for (int r = 0; r < TI + 2; ++r) fm[r] = ok[r] ? p[(size_t)(i0 - 1 + r) * a.nvy] : T(0);
+        for (int r = 0; r < TI + 2; ++r) fm[r] = up_row(r) ? bload<T>(pr, vo[r], 0) : T(0);
     }
     {
-        const T* p = fin + (size_t)k0 * plane;
+        const rsrc_t pr = plane_in(k0);
 #pragma unroll
-        for (int r = 0; r < TI + 2; ++r) fc[r] = ok[r] ? p[(size_t)(i0 - 1 + r) * a.nvy] : T(0);
+        for (int r = 0; r < TI + 2; ++r) fc[r] = bload<T>(pr, vo[r], 0);
     }
+    auto load_ahead = [&](int kk, T (&dst)[TI + 2]) {
+        if (kk < k1) {
+            const rsrc_t pr = plane_in(kk);
+#pragma unroll
+            for (int r = 0; r < TI + 2; ++r) dst[r] = bload<T>(pr, vo[r], 0);
+        } else if (kk < a.nx) {
+            const rsrc_t pr = plane_in(kk);
+#pragma unroll
+            for (int r = 0; r < TI + 2; ++r) dst[r] = down_row(r) ? bload<T>(pr, vo[r], 0) : T(0);
+        } else {
+#pragma unroll
+            for (int r = 0; r < TI + 2; ++r) dst[r] = T(0);   // nothing enters at x = L (Eq 17)
+        }
+    };
+    load_ahead(k0 + 1, fp);
 
     double lv = 0.0, spe = 0.0, ssee = 0.0, stop = 0.0;
     const T dy = T(a.dy);
 
     for (int k = k0; k < k1; ++k) {
-        if (k + 1 < a.nx) {
-            const T* p = fin + (size_t)(k + 1) * plane;
-#pragma unroll
-            for (int r = 0; r < TI + 2; ++r) fp[r] = ok[r] ? p[(size_t)(i0 - 1 + r) * a.nvy] : T(0);
-        } else {
-#pragma unroll
-            for (int r = 0; r < TI + 2; ++r) fp[r] = T(0);   // nothing enters at x = L (Eq 17)
-        }
+        if (k + 2 <= k1) load_ahead(k + 2, fn);
 
         // x sweep: f' = f - c (f - f_up), upwind on the sign of v_x
         T f1[TI + 2];
 #pragma unroll
-        for (int r = 0; r < TI + 2; ++r) {
-            const T diff = c[r] > T(0) ? (fc[r] - fm[r]) : (fp[r] - fc[r]);
-            f1[r] = fc[r] - c[r] * diff;
-        }
+        for (int r = 0; r < TI + 2; ++r) f1[r] = fc[r] - cp[r] * (fc[r] - fm[r]) - cn[r] * (fp[r] - fc[r]);
 
         // v_x sweep by a_x(x_k): upwind on the sign of the plane's Courant number
         const T d = T(a.dxk[k]);
@@ -185,16 +258,16 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T>& a, int wg, double
 #pragma unroll
         for (int r = 1; r <= TI; ++r) {
             const T diff = d > T(0) ? (f1[r] - f1[r - 1]) : (f1[r + 1] - f1[r]);
-            f2[r - 1] = ok[r] ? f1[r] - d * diff : T(0);
+            f2[r - 1] = (rv[r] && jok) ? f1[r] - d * diff : T(0);
         }
         if (d > T(0)) {
 #pragma unroll
             for (int r = 1; r <= TI; ++r)
-                if (ok[r] && i0 - 1 + r == a.nvx - 1) lv += (double)d * (double)f1[r];
+                if (rv[r] && i0 - 1 + r == a.nvx - 1) lv += (double)d * (double)f1[r];
         } else if (d < T(0)) {
 #pragma unroll
             for (int r = 1; r <= TI; ++r)
-                if (ok[r] && i0 - 1 + r == 0) lv -= (double)d * (double)f1[r];
+                if (rv[r] && i0 - 1 + r == 0) lv -= (double)d * (double)f1[r];
         }
 
         // v_y sweep by a_y: the neighbouring column comes from LDS
@@ -221,16 +294,16 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T>& a, int wg, double
         const double s = a.srck[k];
         if (s != 0.0) {
             const T ts = T(s);
-            const T* sp = a.fsrc + j;
 #pragma unroll
             for (int r = 0; r < TI; ++r)
-                if (ok[r + 1]) f3[r] += ts * sp[(size_t)(i0 + r) * a.nvy];
+                if (rv[r + 1] && jok) f3[r] += ts * a.fsrc[(size_t)(i0 + r) * a.nvy + j];
         }
 
-        T* op = a.fout + (size_t)k * plane + j;
+        {
+            const rsrc_t po = plane_out(k);
 #pragma unroll
-        for (int r = 0; r < TI; ++r)
-            if (ok[r + 1]) op[(size_t)(i0 + r) * a.nvy] = f3[r];
+            for (int r = 0; r < TI; ++r) bstore<T>(f3[r], po, vo[r + 1], 0);
+        }
 
         // moments of f^{n+1}
         double sn = 0.0;
@@ -243,7 +316,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T>& a, int wg, double
             for (int r = 0; r < TI; ++r) {
                 const int i = i0 + r;
                 const double v = cell_v(i, a.nvx, a.dvx);
-                if (ok[r + 1] && v < 0.0) {
+                if (rv[r + 1] && jok && v < 0.0) {
                     const double g = -v * (double)f3[r];
                     spe += g;
                     ssee += a.delta[(size_t)i * a.nvy + j] * g;
@@ -254,7 +327,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T>& a, int wg, double
 #pragma unroll
             for (int r = 0; r < TI; ++r) {
                 const double v = cell_v(i0 + r, a.nvx, a.dvx);
-                if (ok[r + 1] && v > 0.0) stop += v * (double)f3[r];
+                if (rv[r + 1] && jok && v > 0.0) stop += v * (double)f3[r];
             }
         }
 
@@ -262,6 +335,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T>& a, int wg, double
         for (int r = 0; r < TI + 2; ++r) {
             fm[r] = fc[r];
             fc[r] = fp[r];
+            fp[r] = fn[r];
         }
     }
 
@@ -269,7 +343,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T>& a, int wg, double
     for (int kk = j; kk < k1 - k0; kk += B) {
         double s = 0.0;
         for (int w = 0; w < nw; ++w) s += wsum[kk * nw + w];
-        a.part_n[(size_t)(k0 + kk) * a.n_it + it] = s;
+        a.part_n[(size_t)it * a.nx + k0 + kk] = s;
     }
     lv = wave_sum(lv);
     spe = wave_sum(spe);
@@ -290,7 +364,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T>& a, int wg, double
             t2 += red[w * 4 + 2];
             t3 += red[w * 4 + 3];
         }
-        a.part_lv[wg] = t0;
+        a.part_lv[kci * a.n_it + it] = t0;
         if (k0 == 0) {
             a.part_wall[it * 2 + 0] = t1;
             a.part_wall[it * 2 + 1] = t2;
@@ -339,7 +413,7 @@ __device__ __forceinline__ void moments_tile(const SweepArgs<T>& a, int wg, doub
     for (int kk = j; kk < k1 - k0; kk += blockDim.x) {
         double s = 0.0;
         for (int w = 0; w < nw; ++w) s += wsum[kk * nw + w];
-        a.part_n[(size_t)(k0 + kk) * a.n_it + it] = s;
+        a.part_n[(size_t)it * a.nx + k0 + kk] = s;
     }
     spe = wave_sum(spe);
     ssee = wave_sum(ssee);
@@ -366,59 +440,117 @@ __device__ __forceinline__ void moments_tile(const SweepArgs<T>& a, int wg, doub
     }
 }
 
+__device__ __forceinline__ void reduce_tiles(const ReduceArgs& a, double* sh)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < a.nx) {
+        double s = 0.0;
+#pragma unroll 16
+        for (int u = 0; u < a.n_it; ++u) s += a.part_n[(size_t)u * a.nx + k];
+        a.plane_sum[k] = s;
+    }
+    if (blockIdx.x != 0) return;
+    const int t = threadIdx.x;
+    double pe = 0.0, see = 0.0, top = 0.0, lv = 0.0;
+    for (int u = t; u < a.n_it; u += blockDim.x) {
+        pe += a.part_wall[2 * u];
+        see += a.part_wall[2 * u + 1];
+        top += a.part_top[u];
+    }
+#pragma unroll 4
+    for (int w = t; w < a.nwg; w += blockDim.x) lv += a.part_lv[w];
+    pe = block_sum(pe, sh);
+    see = block_sum(see, sh);
+    top = block_sum(top, sh);
+    lv = block_sum(lv, sh);
+    if (t == 0) {
+        a.wall_sum[0] = pe;
+        a.wall_sum[1] = see;
+        a.wall_sum[2] = top;
+        a.wall_sum[3] = lv;
+    }
+}
+
 // ---------------------------------------------------------------- field
 
 struct FieldArgs {
-    const double* __restrict__ part_n;
-    const double* __restrict__ part_wall;
-    const double* __restrict__ part_top;
-    const double* __restrict__ part_lv;
+    const double* __restrict__ plane_sum;   // [nx]
+    const double* __restrict__ wall_sum;    // [4]
     const double* __restrict__ consts;  // zsum, srcnorm, injected per step, Eq 15 prefactor
     double* __restrict__ ne;
     double* __restrict__ ex;
     double* __restrict__ dxk;
     DevState* __restrict__ st;
     fk_state* __restrict__ ring;
-    int nx, n_it, nwg, advance;
+    int nx, advance;
     uint32_t mask;
     int emission_norm, trace_stride, trace_cap;
     double dx, dv2, dt, dvx, ex_ext;
 };
 
+// Inclusive prefix sum over the 64 lanes of a wavefront (fixed order).
+__device__ __forceinline__ double wave_scan(double v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const double u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
 // Reduction of the moment partials of the new f, the 1D field solve and the
-// wall bookkeeping; one workgroup of kFieldThreads threads.
+// wall bookkeeping; one workgroup of kFieldThreads threads.  sh holds
+// 2 * kFieldThreads doubles.
 __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
 {
     const int t = threadIdx.x;
     const int T = blockDim.x;
+    const int lane = t & 63, wave = t >> 6, nw = T >> 6;
     const int seg = (a.nx + T - 1) / T;
     const int kb = min(t * seg, a.nx), ke = min(kb + seg, a.nx);
 
-    // electron density per plane (sum over the v_x tiles, fixed order)
+    // electron density per plane (the sweep has reduced the v_x tiles)
     double local = 0.0;
     for (int k = kb; k < ke; ++k) {
-        double s = 0.0;
-        for (int u = 0; u < a.n_it; ++u) s += a.part_n[(size_t)k * a.n_it + u];
-        const double nk = s * a.dv2;
+        const double nk = a.plane_sum[k] * a.dv2;
         a.ne[k] = nk;
         local += nk;
     }
-
-    // exclusive prefix over the thread segments (Hillis-Steele on LDS)
-    double* s0 = sh;
-    double* s1 = sh + T;
-    s0[t] = local;
-    __syncthreads();
-    for (int off = 1; off < T; off <<= 1) {
-        double v = s0[t];
-        if (t >= off) v += s0[t - off];
-        s1[t] = v;
-        __syncthreads();
-        double* tmp = s0; s0 = s1; s1 = tmp;
+    double pe = 0.0, see = 0.0, top = 0.0, lv = 0.0;
+    if (t == 0) {
+        pe = a.wall_sum[0];
+        see = a.wall_sum[1];
+        top = a.wall_sum[2];
+        lv = a.advance ? a.wall_sum[3] : 0.0;
     }
-    const double below0 = t > 0 ? s0[t - 1] : 0.0;
-    const double total = s0[T - 1];
+
+    // exclusive prefix of the segment sums over the workgroup: wave scans,
+    // then a scan of the wave totals
+    const double incl = wave_scan(local);
+    double excl = __shfl_up(incl, 1, 64);
+    if (lane == 0) excl = 0.0;
+    double* wtot = sh;              // [nw]
+    double* red = sh + 64;          // [nw][5]
+    if (lane == 63) wtot[wave] = incl;
+    pe = wave_sum(pe);
+    see = wave_sum(see);
+    top = wave_sum(top);
+    lv = wave_sum(lv);
+    if (lane == 0) {
+        red[wave * 5 + 0] = pe;
+        red[wave * 5 + 1] = see;
+        red[wave * 5 + 2] = top;
+        red[wave * 5 + 3] = lv;
+    }
     __syncthreads();
+    double wave_below = 0.0, total = 0.0;
+    for (int w = 0; w < nw; ++w) {
+        if (w < wave) wave_below += wtot[w];
+        total += wtot[w];
+    }
+    const double below0 = wave_below + excl;
 
     const DevState old = *a.st;
     double sig = old.sigma, sig_lo = old.sigma_lo;
@@ -446,20 +578,20 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
         cmax = fmax(cmax, fabs(d));
         run += nk;
     }
-    cmax = block_max(cmax, s1);
-
-    double pe = 0.0, see = 0.0, top = 0.0, lv = 0.0;
-    for (int u = t; u < a.n_it; u += T) {
-        pe += a.part_wall[2 * u];
-        see += a.part_wall[2 * u + 1];
-        top += a.part_top[u];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) cmax = fmax(cmax, __shfl_xor(cmax, o, 64));
+    if (lane == 0) red[wave * 5 + 4] = cmax;
+    __syncthreads();
+    if (t == 0) {
+        pe = see = top = lv = cmax = 0.0;
+        for (int w = 0; w < nw; ++w) {
+            pe += red[w * 5 + 0];
+            see += red[w * 5 + 1];
+            top += red[w * 5 + 2];
+            lv += red[w * 5 + 3];
+            cmax = fmax(cmax, red[w * 5 + 4]);
+        }
     }
-    if (a.advance)
-        for (int w = t; w < a.nwg; w += T) lv += a.part_lv[w];
-    pe = block_sum(pe, s1);
-    see = block_sum(see, s1);
-    top = block_sum(top, s1);
-    lv = block_sum(lv, s1);
 
     if (t == 0) {
         const bool x_on = a.mask & FK_PHYS_X;

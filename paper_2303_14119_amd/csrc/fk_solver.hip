@@ -9,6 +9,7 @@
 #include <new>
 
 #include "fk_kernels.h"
+#include "fk_sweep_fast.h"
 
 namespace fk {
 
@@ -111,11 +112,24 @@ __global__ void __launch_bounds__(kFieldThreads) k_tables_norm(TableArgs a)
 
 // ---------------------------------------------------------------- kernels
 
+// Tiles of a launch: blockIdx -> (x chunk, entry of the launch's v_x tile
+// list), remapped so each XCD takes a contiguous range.
 template <typename T, int TI, int MAXB>
 __global__ void __launch_bounds__(MAXB) k_sweep(SweepArgs<T> a)
 {
     extern __shared__ double smem[];
-    sweep_tile<T, TI>(a, xcd_remap(blockIdx.x, gridDim.x), smem);
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int it = a.tile_list[wg % a.n_list];
+    sweep_fast_dispatch<T, TI>(a, wg, it, wg / a.n_list, smem);
+}
+
+template <typename T, int TI, int MAXB>
+__global__ void __launch_bounds__(MAXB) k_sweep_generic(SweepArgs<T> a)
+{
+    extern __shared__ double smem[];
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int it = a.tile_list[wg % a.n_list];
+    sweep_body<T, TI, true>(a, wg, it, wg / a.n_list, smem);
 }
 
 template <typename T, int TI>
@@ -123,6 +137,12 @@ __global__ void __launch_bounds__(1024) k_moments(SweepArgs<T> a)
 {
     extern __shared__ double smem[];
     moments_tile<T, TI>(a, blockIdx.x, smem);
+}
+
+__global__ void __launch_bounds__(256) k_reduce(ReduceArgs a)
+{
+    __shared__ double sh[256];
+    reduce_tiles(a, sh);
 }
 
 __global__ void __launch_bounds__(kFieldThreads) k_field(FieldArgs a)
@@ -157,9 +177,10 @@ struct fk_ctx {
     int64_t drained_step = -1;    // last step whose record has been drained
     // profiling
     bool prof = false;
-    struct Ev { hipEvent_t a, b, c; };   // sweep a->b, field b->c
+    struct Ev { hipEvent_t a, b; };   // sweep launch a->b
     std::vector<Ev> events;
     std::vector<hipEvent_t> spare;
+    std::vector<int> tile_order;   // host copy of the tile list (kept alive for the async upload)
 };
 
 namespace {
@@ -201,16 +222,27 @@ SweepArgs<T> sweep_args(const fk_ctx* c, int from)
     a.dt_dx = c->L.dt / c->L.dx;
     a.dy = c->L.dy;
     a.x_on = (c->p.physics_mask & FK_PHYS_X) ? 1 : 0;
-    a.tile_base = 0;
-    a.nwg_total = c->L.nwg;
+    a.tile_list = c->b.tiles;
+    a.n_list = c->L.n_it;
     return a;
 }
 
 template <typename T, int TI, int MAXB>
 void launch_sweep_t(const fk_ctx* c, int from, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_sweep<T, TI, MAXB>), dim3(c->L.nwg), dim3(c->L.block), c->L.lds_sweep, s,
-                       sweep_args<T>(c, from));
+    SweepArgs<T> a = sweep_args<T>(c, from);
+    if (c->L.n_fast > 0) {
+        a.tile_list = c->b.tiles;
+        a.n_list = c->L.n_fast;
+        hipLaunchKernelGGL((k_sweep<T, TI, MAXB>), dim3(c->L.n_fast * c->L.n_kc), dim3(c->L.block),
+                           c->L.lds_sweep, s, a);
+    }
+    if (c->L.n_generic > 0) {
+        a.tile_list = c->b.tiles + c->L.n_fast;
+        a.n_list = c->L.n_generic;
+        hipLaunchKernelGGL((k_sweep_generic<T, TI, MAXB>), dim3(c->L.n_generic * c->L.n_kc),
+                           dim3(c->L.block), c->L.lds_sweep, s, a);
+    }
 }
 
 void launch_sweep(const fk_ctx* c, int from, hipStream_t s)
@@ -251,10 +283,8 @@ void launch_moments(const fk_ctx* c, hipStream_t s)
 FieldArgs field_args(const fk_ctx* c, int advance)
 {
     FieldArgs a{};
-    a.part_n = c->b.part_n;
-    a.part_wall = c->b.part_wall;
-    a.part_top = c->b.part_top;
-    a.part_lv = c->b.part_lv;
+    a.plane_sum = c->b.plane_sum;
+    a.wall_sum = c->b.wall_sum;
     a.consts = c->b.consts;
     a.ne = c->b.ne;
     a.ex = c->b.ex;
@@ -262,8 +292,6 @@ FieldArgs field_args(const fk_ctx* c, int advance)
     a.st = c->b.st;
     a.ring = c->b.ring;
     a.nx = c->p.nx;
-    a.n_it = c->L.n_it;
-    a.nwg = c->L.nwg;
     a.advance = advance;
     a.mask = c->p.physics_mask;
     a.emission_norm = c->p.emission_norm;
@@ -279,6 +307,17 @@ FieldArgs field_args(const fk_ctx* c, int advance)
 
 void launch_field(const fk_ctx* c, int advance, hipStream_t s)
 {
+    ReduceArgs r{};
+    r.part_n = c->b.part_n;
+    r.part_wall = c->b.part_wall;
+    r.part_top = c->b.part_top;
+    r.part_lv = c->b.part_lv;
+    r.plane_sum = c->b.plane_sum;
+    r.wall_sum = c->b.wall_sum;
+    r.nx = c->p.nx;
+    r.n_it = c->L.n_it;
+    r.nwg = c->L.nwg;
+    hipLaunchKernelGGL(k_reduce, dim3((c->p.nx + 255) / 256), dim3(256), 0, s, r);
     hipLaunchKernelGGL(k_field, dim3(1), dim3(kFieldThreads), 0, s, field_args(c, advance));
 }
 
@@ -303,7 +342,9 @@ int alloc_buffers(fk_ctx* c, void* fa, void* fb)
                  o_pn = take((size_t)p.nx * L.n_it * 8), o_pw = take((size_t)L.n_it * 16),
                  o_pt = take((size_t)L.n_it * 8), o_plv = take((size_t)L.nwg * 8),
                  o_ne = take(p.nx * 8), o_ex = take(p.nx * 8), o_dxk = take(p.nx * 8),
-                 o_consts = take(64), o_st = take(sizeof(DevState)),
+                 o_consts = take(64), o_tiles = take((size_t)L.n_it * sizeof(int)),
+                 o_psum = take((size_t)p.nx * 8), o_wsum = take(4 * 8),
+                 o_st = take(sizeof(DevState)),
                  o_ring = take((size_t)p.trace_cap * sizeof(fk_state));
     if (hipMalloc(&c->pool, off) != hipSuccess) {
         c->pool = nullptr;
@@ -324,9 +365,22 @@ int alloc_buffers(fk_ctx* c, void* fa, void* fb)
     c->b.ex = (double*)(base + o_ex);
     c->b.dxk = (double*)(base + o_dxk);
     c->b.consts = (double*)(base + o_consts);
+    c->b.tiles = (int*)(base + o_tiles);
+    c->b.plane_sum = (double*)(base + o_psum);
+    c->b.wall_sum = (double*)(base + o_wsum);
     c->b.st = (DevState*)(base + o_st);
     c->b.ring = (fk_state*)(base + o_ring);
     FK_HIP(c, hipMemsetAsync(c->pool, 0, off, c->stream));
+    {
+        std::vector<int> order;
+        for (int it = 0; it < L.n_it; ++it)
+            if (tile_is_fast(it, L.ti, p.nvx)) order.push_back(it);
+        for (int it = 0; it < L.n_it; ++it)
+            if (!tile_is_fast(it, L.ti, p.nvx)) order.push_back(it);
+        c->tile_order = order;
+        FK_HIP(c, hipMemcpyAsync(c->b.tiles, c->tile_order.data(), order.size() * sizeof(int),
+                                 hipMemcpyHostToDevice, c->stream));
+    }
     const size_t fbytes = (size_t)L.cells * L.elem;
     if (fa) {
         c->own_f = false;
@@ -472,7 +526,6 @@ void release(fk_ctx* c)
     for (auto& e : c->events) {
         (void)hipEventDestroy(e.a);
         (void)hipEventDestroy(e.b);
-        (void)hipEventDestroy(e.c);
     }
     for (auto e : c->spare) (void)hipEventDestroy(e);
     if (c->own_f) {
@@ -560,15 +613,17 @@ extern "C" int fk_step(fk_ctx* c, int64_t n)
     if (!c || n < 0) return set_error(c ? &c->err : nullptr, FK_E_INVALID, "bad arguments to fk_step");
     if (c->sticky) return c->sticky;
     if (c->prof) {
+        // two events per step, around the sweep launch only; the interval
+        // from one step's sweep end to the next step's sweep start holds the
+        // reduction and field kernels
         for (int64_t s = 0; s < n; ++s) {
-            hipEvent_t e0 = get_event(c), e1 = get_event(c), e2 = get_event(c);
-            if (!e0 || !e1 || !e2) return set_error(&c->err, FK_E_HIP, "hipEventCreate failed");
+            hipEvent_t e0 = get_event(c), e1 = get_event(c);
+            if (!e0 || !e1) return set_error(&c->err, FK_E_HIP, "hipEventCreate failed");
             FK_HIP(c, hipEventRecord(e0, c->stream));
             launch_sweep(c, c->cur, c->stream);
             FK_HIP(c, hipEventRecord(e1, c->stream));
             launch_field(c, 1, c->stream);
-            FK_HIP(c, hipEventRecord(e2, c->stream));
-            c->events.push_back({e0, e1, e2});
+            c->events.push_back({e0, e1});
             c->cur ^= 1;
         }
         FK_HIP(c, hipGetLastError());
@@ -709,7 +764,6 @@ extern "C" int fk_set_profiling(fk_ctx* c, int on)
     for (auto& e : c->events) {
         c->spare.push_back(e.a);
         c->spare.push_back(e.b);
-        c->spare.push_back(e.c);
     }
     c->events.clear();
     c->prof = on != 0;
@@ -722,14 +776,16 @@ extern "C" int fk_kernel_times(fk_ctx* c, double* sweep_ms, int64_t* sweep_n, do
     FK_HIP(c, hipStreamSynchronize(c->stream));
     double t[2] = {0, 0};
     int64_t n[2] = {0, 0};
-    for (auto& e : c->events) {
+    for (size_t m = 0; m < c->events.size(); ++m) {
         float ms = 0;
-        FK_HIP(c, hipEventElapsedTime(&ms, e.a, e.b));
+        FK_HIP(c, hipEventElapsedTime(&ms, c->events[m].a, c->events[m].b));
         t[0] += ms;
-        FK_HIP(c, hipEventElapsedTime(&ms, e.b, e.c));
-        t[1] += ms;
         n[0] += 1;
-        n[1] += 1;
+        if (m + 1 < c->events.size()) {
+            FK_HIP(c, hipEventElapsedTime(&ms, c->events[m].b, c->events[m + 1].a));
+            t[1] += ms;
+            n[1] += 1;
+        }
     }
     if (sweep_ms) *sweep_ms = t[0];
     if (sweep_n) *sweep_n = n[0];

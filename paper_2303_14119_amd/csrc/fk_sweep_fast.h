@@ -1,0 +1,247 @@
+// fk_sweep_fast.h -- the sweep of one tile whose v_x rows split at a
+// compile-time row S: rows r < S have v_x <= 0 (their upwind x neighbour is
+// the plane above), rows r >= S have v_x > 0 (upwind is the plane below).
+// Rows are r = 0 .. TI+1 for v_x rows i = i0 - 1 + r (r = 0 and r = TI+1
+// are the halo rows of the v_x sweep).  Used for every tile of a grid
+// whose v_x tiles do not straddle v_x = 0 except at a halo row and whose
+// last tile is full; other tiles take the generic body.
+//
+// Per row the thread keeps the two x planes the upwind update reads plus
+// one prefetched plane.  Rows outside the grid (the halo below the first
+// tile, above the last) and lanes past nvy read 0 and store nothing through
+// the buffer range check, so the body has no per-row lane masks.
+#pragma once
+
+#include "fk_kernels.h"
+
+namespace fk {
+
+template <typename T, int TI, int S>
+__device__ __forceinline__ void sweep_fast(const SweepArgs<T>& a, int wg, int it, int kci, double* smem)
+{
+    const int i0 = it * TI;
+    const int k0 = kci * a.kc;
+    const int k1 = min(k0 + a.kc, a.nx);
+    const int j = threadIdx.x;
+    const int B = blockDim.x;
+    const int nw = B >> 6;
+    const int lane = j & 63, wave = j >> 6;
+    const bool jok = j < a.nvy;
+    const int W = B + 2;
+    const size_t plane = (size_t)a.nvx * a.nvy;
+    const uint32_t pbytes = (uint32_t)(plane * sizeof(T));
+    const int rb = a.nvy * (int)sizeof(T);
+    const int es = (int)sizeof(T);
+    const bool first = it == 0;
+    const bool last = i0 + TI >= a.nvx;
+    // lane byte offsets within a plane: output rows r = 1..TI at vb + (r-1)*rb,
+    // halo rows at vlo / vhi (out of range outside the grid)
+    const int vb = jok ? i0 * rb + j * es : kIdleLaneOffset;
+    const int vlo = (jok && !first) ? (i0 - 1) * rb + j * es : kIdleLaneOffset;
+    const int vhi = (jok && !last) ? (i0 + TI) * rb + j * es : kIdleLaneOffset;
+
+    T* xb = reinterpret_cast<T*>(smem);                       // [2][TI][W]
+    double* wsum = reinterpret_cast<double*>(xb + 2 * TI * W); // [kc][nw]
+    double* red = wsum + a.kc * nw;                           // [nw][4]
+    for (int m = j; m < 2 * TI; m += B) {
+        xb[m * W] = T(0);
+        xb[m * W + W - 1] = T(0);
+    }
+
+    T c[TI + 2];
+#pragma unroll
+    for (int r = 0; r < TI + 2; ++r) {
+        const int i = i0 - 1 + r;
+        c[r] = a.x_on ? T(cell_v(i, a.nvx, a.dvx) * a.dt_dx) : T(0);
+    }
+
+    auto plane_in = [&](int kk) { return make_rsrc(a.fin + (size_t)kk * plane, pbytes); };
+    auto ldrow = [&](const rsrc_t& pr, int r) -> T {
+        if (r == 0) return bload<T>(pr, vlo, 0);
+        if (r == TI + 1) return bload<T>(pr, vhi, 0);
+        return bload<T>(pr, vb, (r - 1) * rb);
+    };
+
+    // w0/w1: the two planes the row's upwind update reads; w2: prefetch.
+    //   rows r < S  (v_x <= 0): w0 = f(k),   w1 = f(k+1)
+    //   rows r >= S (v_x > 0):  w0 = f(k-1), w1 = f(k)
+    T w0[TI + 2], w1[TI + 2], w2[TI + 2];
+    {
+        const rsrc_t pk = plane_in(k0);
+        const bool has_up = k0 + 1 < a.nx;           // nothing enters at x = L (Eq 17)
+        const rsrc_t pu = plane_in(has_up ? k0 + 1 : k0);
+#pragma unroll
+        for (int r = 0; r < S; ++r) {
+            w0[r] = ldrow(pk, r);
+            w1[r] = has_up ? ldrow(pu, r) : T(0);
+        }
+#pragma unroll
+        for (int r = S; r < TI + 2; ++r) w1[r] = ldrow(pk, r);
+        if (k0 == 0) {
+            // below the dielectric: the emission row of this step (Eq 15)
+            const double gs = a.st->gscale;
+#pragma unroll
+            for (int r = S; r < TI + 2; ++r) {
+                const int i = i0 - 1 + r;
+                w0[r] = (jok && i < a.nvx) ? T(gs * a.ghat[(size_t)i * a.nvy + j]) : T(0);
+            }
+        } else {
+            const rsrc_t pd = plane_in(k0 - 1);
+#pragma unroll
+            for (int r = S; r < TI + 2; ++r) w0[r] = ldrow(pd, r);
+        }
+    }
+
+    const int nvl = a.nvy;
+    const T dy = T(a.dy);
+    double lv = 0.0, spe = 0.0, ssee = 0.0, stop = 0.0;
+    const rsrc_t psrc = make_rsrc(a.fsrc, pbytes);
+
+    for (int k = k0; k < k1; ++k) {
+        // prefetch the planes of the next iteration
+        if (k + 1 < k1) {
+            const rsrc_t p1 = plane_in(k + 1);
+#pragma unroll
+            for (int r = S; r < TI + 2; ++r) w2[r] = ldrow(p1, r);
+            if (k + 2 < a.nx) {
+                const rsrc_t p2 = plane_in(k + 2);
+#pragma unroll
+                for (int r = 0; r < S; ++r) w2[r] = ldrow(p2, r);
+            } else {
+#pragma unroll
+                for (int r = 0; r < S; ++r) w2[r] = T(0);
+            }
+        }
+
+        // x sweep (upwind on the sign of v_x)
+        T f1[TI + 2];
+#pragma unroll
+        for (int r = 0; r < TI + 2; ++r)
+            f1[r] = r < S ? w0[r] - c[r] * (w1[r] - w0[r]) : w1[r] - c[r] * (w1[r] - w0[r]);
+
+        // v_x sweep by a_x(x_k), upwind on the sign of the plane's Courant number
+        const T d = T(a.dxk[k]);
+        T f2[TI];
+        if (d > T(0)) {
+#pragma unroll
+            for (int r = 1; r <= TI; ++r) f2[r - 1] = f1[r] - d * (f1[r] - f1[r - 1]);
+            if (last) lv += (double)d * (double)f1[TI];          // leaves through +v_max
+        } else {
+#pragma unroll
+            for (int r = 1; r <= TI; ++r) f2[r - 1] = f1[r] - d * (f1[r + 1] - f1[r]);
+            if (first) lv -= (double)d * (double)f1[1];          // leaves through -v_max
+        }
+
+        // v_y sweep by a_y: the neighbouring column comes from LDS
+        T* buf = xb + (k & 1) * TI * W;
+#pragma unroll
+        for (int r = 0; r < TI; ++r) buf[r * W + j + 1] = f2[r];
+        __syncthreads();
+        T f3[TI];
+        if (dy > T(0)) {
+#pragma unroll
+            for (int r = 0; r < TI; ++r) f3[r] = f2[r] - dy * (f2[r] - buf[r * W + j]);
+            if (j == nvl - 1) {
+#pragma unroll
+                for (int r = 0; r < TI; ++r) lv += (double)dy * (double)f2[r];
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < TI; ++r) f3[r] = f2[r] - dy * (buf[r * W + j + 2] - f2[r]);
+            if (j == 0) {
+#pragma unroll
+                for (int r = 0; r < TI; ++r) lv -= (double)dy * (double)f2[r];
+            }
+        }
+
+        // band source (Eq 7)
+        const double s = a.srck[k];
+        if (s != 0.0) {
+            const T ts = T(s);
+#pragma unroll
+            for (int r = 0; r < TI; ++r) f3[r] += ts * bload<T>(psrc, vb, r * rb);
+        }
+
+        {
+            const rsrc_t po = make_rsrc(a.fout + (size_t)k * plane, pbytes);
+#pragma unroll
+            for (int r = 0; r < TI; ++r) bstore<T>(f3[r], po, vb, r * rb);
+        }
+
+        // moments of f^{n+1}
+        double sn = 0.0;
+#pragma unroll
+        for (int r = 0; r < TI; ++r) sn += (double)f3[r];
+        sn = wave_sum(jok ? sn : 0.0);
+        if (lane == 0) wsum[(k - k0) * nw + wave] = sn;
+        if (k == 0 && jok) {
+#pragma unroll
+            for (int r = 1; r < (S < TI + 1 ? S : TI + 1); ++r) {   // output rows with v_x <= 0
+                const int i = i0 - 1 + r;
+                const double g = -cell_v(i, a.nvx, a.dvx) * (double)f3[r - 1];
+                spe += g;
+                ssee += a.delta[(size_t)i * a.nvy + j] * g;
+            }
+        }
+        if (k == a.nx - 1 && jok) {
+#pragma unroll
+            for (int r = (S > 1 ? S : 1); r <= TI; ++r)                // output rows with v_x > 0
+                stop += cell_v(i0 - 1 + r, a.nvx, a.dvx) * (double)f3[r - 1];
+        }
+
+        if (k + 1 < k1) {
+#pragma unroll
+            for (int r = 0; r < TI + 2; ++r) {
+                w0[r] = w1[r];
+                w1[r] = w2[r];
+            }
+        }
+    }
+
+    __syncthreads();
+    for (int kk = j; kk < k1 - k0; kk += B) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += wsum[kk * nw + w];
+        a.part_n[(size_t)it * a.nx + k0 + kk] = s;
+    }
+    lv = wave_sum(lv);
+    spe = wave_sum(spe);
+    ssee = wave_sum(ssee);
+    stop = wave_sum(stop);
+    if (lane == 0) {
+        red[wave * 4 + 0] = lv;
+        red[wave * 4 + 1] = spe;
+        red[wave * 4 + 2] = ssee;
+        red[wave * 4 + 3] = stop;
+    }
+    __syncthreads();
+    if (j == 0) {
+        double t0 = 0, t1 = 0, t2 = 0, t3 = 0;
+        for (int w = 0; w < nw; ++w) {
+            t0 += red[w * 4 + 0];
+            t1 += red[w * 4 + 1];
+            t2 += red[w * 4 + 2];
+            t3 += red[w * 4 + 3];
+        }
+        a.part_lv[kci * a.n_it + it] = t0;
+        if (k0 == 0) {
+            a.part_wall[it * 2 + 0] = t1;
+            a.part_wall[it * 2 + 1] = t2;
+        }
+        if (k1 == a.nx) a.part_top[it] = t3;
+    }
+    (void)wg;
+}
+
+template <typename T, int TI>
+__device__ __forceinline__ void sweep_fast_dispatch(const SweepArgs<T>& a, int wg, int it, int kci, double* smem)
+{
+    switch (tile_split(it, TI, a.nvx)) {
+    case 0: sweep_fast<T, TI, 0>(a, wg, it, kci, smem); break;
+    case 1: sweep_fast<T, TI, 1>(a, wg, it, kci, smem); break;
+    case TI + 1: sweep_fast<T, TI, TI + 1>(a, wg, it, kci, smem); break;
+    default: sweep_fast<T, TI, TI + 2>(a, wg, it, kci, smem); break;
+    }
+}
+
+}  // namespace fk

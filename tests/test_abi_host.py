@@ -1,0 +1,95 @@
+"""The C-ABI library loads, exports every function include/flashkin.h
+declares, and its host-only logic (parameter validation, launch shape,
+saturation test) behaves as documented.  No GPU is touched."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2303_14119_amd import flashkin as fk
+from paper_2303_14119_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "flashkin.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fk_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 19
+    lib = C.CDLL(fk.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_the_header():
+    assert set(declared_functions()) <= set(fk.SIGNATURES)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_validate_workloads(dtype):
+    for cfg in (W.c0(), W.c1(), W.c4(), W.paper_default()):
+        info = fk.validate(fk.make_params(cfg, dtype))
+        assert info["cells"] == cfg["nx"] * cfg["nvx"] * cfg["nvy"]
+        assert 0 < info["courant_x"] <= 1 and 0 <= info["courant_vy"] <= 1
+        assert info["block"] % 64 == 0 and info["block"] >= cfg["nvy"]
+
+
+def test_default_time_step_matches_the_cfl_rule():
+    info = fk.validate(fk.make_params(W.c0(), "f64"))
+    assert info["dt"] == pytest.approx(3.7489257835957387e-13, rel=1e-15)
+    assert info["courant_x"] == pytest.approx(0.8859375, rel=1e-12)
+    assert info["courant_vy"] == pytest.approx(0.5625, rel=1e-12)
+
+
+def bad(**kw):
+    cfg = W.c0()
+    extra = {k: kw.pop(k) for k in list(kw) if k in ("tile_rows", "tile_planes", "trace_cap", "trace_stride")}
+    cfg.update(kw)
+    p = fk.make_params(cfg, "f32", **extra)
+    return fk.fk_validate(C.byref(p), None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(nx=0), fk.E_INVALID), (dict(nvy=1025), fk.E_INVALID), (dict(length=-1.0), fk.E_INVALID),
+    (dict(t_se_ev=0.0), fk.E_INVALID), (dict(x_src_lo=2e-5, x_src_hi=1e-5), fk.E_INVALID),
+    (dict(physics_mask=64), fk.E_INVALID), (dict(emission_norm=2), fk.E_INVALID),
+    (dict(tile_rows=3), fk.E_INVALID), (dict(trace_cap=0), fk.E_INVALID),
+    (dict(dt=1e-11), fk.E_CFL), (dict(ey=-1e9, dt=3e-13), fk.E_CFL),
+])
+def test_validate_rejects(kw, code):
+    assert bad(**kw) == code
+    assert fk.fk_last_error(None)
+
+
+def test_struct_size_and_version_are_checked():
+    p = fk.make_params(W.c0())
+    p.struct_size -= 8
+    assert fk.fk_validate(C.byref(p), None) == fk.E_INVALID
+    p = fk.make_params(W.c0())
+    p.abi_version = 99
+    assert fk.fk_validate(C.byref(p), None) == fk.E_INVALID
+
+
+def rec(t, sigma, gpe, gsee):
+    r = fk.fk_state()
+    r.t, r.sigma, r.g_pe, r.g_see = t, sigma, gpe, gsee
+    return r
+
+
+def test_saturation_check():
+    """Section 2: converged when sigma and the fluxes change by less than the
+    tolerance over the window."""
+    flat = [rec(i * 1e-12, 1e-5, 1e24, 1e24) for i in range(200)]
+    assert fk.saturation_check(flat, 50e-12, 1e-3)
+    assert not fk.saturation_check(flat[:40], 50e-12, 1e-3)        # shorter than the window
+    rising = [rec(i * 1e-12, 1e-5 * (1 + 1e-4 * i), 1e24, 1e24) for i in range(200)]
+    assert not fk.saturation_check(rising, 50e-12, 1e-3)             # 0.5% over the window
+    assert fk.saturation_check(rising, 50e-12, 1e-2)
+    empty = [rec(i * 1e-12, 0.0, 0.0, 0.0) for i in range(200)]
+    assert not fk.saturation_check(empty, 50e-12, 1e-3)              # nothing has arrived yet
