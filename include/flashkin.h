@@ -210,6 +210,52 @@ int fk_set_profiling(fk_ctx* ctx, int on);
 int fk_kernel_times(fk_ctx* ctx, double* sweep_ms, int64_t* sweep_count, double* field_ms,
                     int64_t* field_count);
 
+/* Tiling autotuner (a project addition; the paper prescribes no kernel
+ * layout).  Times trial_steps >= 2 steps for each candidate tiling (v_x rows
+ * 4/8/16 x x planes 16/32/64/128 that fit) and keeps the fastest.  The state
+ * (f, sigma, step, trace history) is the same afterwards.  The chosen layout
+ * is written to *chosen if it is not NULL. */
+int fk_autotune(fk_ctx* ctx, int trial_steps, fk_info* chosen);
+
+/* ---- batched instances ---------------------------------------------------
+ * n independent runs of uneven sizes (the parameter sweep that feeds the
+ * surrogate) advanced together: one persistent sweep launch per step takes
+ * (instance, x chunk, v_x tiles) work items largest first, followed by one
+ * reduction and one field launch for all instances; steps are replayed from
+ * HIP graphs.  Every instance is FK_F32 with nvy <= 256.  Each instance
+ * starts at f = 0, sigma = 0.  If autotune != 0 the tiling and the
+ * persistent grid size are chosen by timing short trial runs first (the
+ * instances are reset to f = 0 afterwards). */
+typedef struct {
+    int32_t n;             /* instances */
+    int32_t tile_rows;     /* v_x rows per tile */
+    int32_t tile_planes;   /* x planes per tile of instance 0 */
+    int32_t grid;          /* workgroups of the persistent launch */
+    int32_t items;         /* work items per step */
+    int64_t lds_bytes;     /* LDS per workgroup */
+    int64_t cells;         /* sum of nx * nvx * nvy over the instances */
+    int32_t schedule;      /* 0: items from an atomic counter, 1: static round-robin */
+    int32_t reserved;
+} fk_batch_info_t;
+
+int fk_batch_create(const fk_params* params, int n, void* stream, int autotune, fk_batch** out);
+int fk_batch_destroy(fk_batch* batch);
+
+/* Queue nsteps steps of every instance (asynchronous). */
+int fk_batch_step(fk_batch* batch, int64_t nsteps);
+
+/* Wait; returns the first instance error (CFL, non-finite) and its index in
+ * *first_bad (-1 if none; may be NULL). */
+int fk_batch_sync(fk_batch* batch, int* first_bad);
+
+/* Non-owning view of instance i, valid until fk_batch_destroy: the fk_read_*,
+ * fk_write_state, fk_saturated and fk_query calls work on it; fk_step on a
+ * view returns FK_E_STATE. */
+int fk_batch_get(fk_batch* batch, int i, fk_ctx** view);
+
+int fk_batch_info(const fk_batch* batch, fk_batch_info_t* out);
+const char* fk_batch_last_error(const fk_batch* batch);
+
 #ifdef __cplusplus
 }
 #endif

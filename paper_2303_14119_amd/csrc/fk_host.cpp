@@ -47,7 +47,8 @@ int derive_layout(const fk_params* p, Layout* L, std::string* why)
     if (p->trace_stride < 1 || p->trace_cap < 1) return bad("trace_stride and trace_cap must be >= 1");
     if (p->tile_rows != 0 && p->tile_rows != 4 && p->tile_rows != 8 && p->tile_rows != 16)
         return bad("tile_rows must be 0, 4, 8 or 16");
-    if (p->tile_planes < 0 || p->tile_planes > 128) return bad("tile_planes must be in [0, 128]");
+    if (p->tile_planes != 0 && (p->tile_planes < 4 || p->tile_planes > 128))
+        return bad("tile_planes must be 0 or in [4, 128]");
 
     const int64_t cells = (int64_t)p->nx * p->nvx * p->nvy;
     if (cells > ((int64_t)1 << 40)) return bad("grid too large");
@@ -112,10 +113,14 @@ int derive_layout(const fk_params* p, Layout* L, std::string* why)
     l.lds_moments = (size_t)kc * (l.block / 64) * 8 + (size_t)(l.block / 64) * 4 * 8;
     if (l.lds_sweep > kLdsBudget) return bad("tile needs more LDS than a workgroup has; lower tile_rows or tile_planes");
 
+    // partial buffers are sized for the smallest tile (4 rows, 4 planes) so a
+    // context can be retiled without reallocating
+    l.n_it_cap = (p->nvx + 3) / 4;
+    l.nwg_cap = l.n_it_cap * ((p->nx + 3) / 4);
     const uint64_t v2 = (uint64_t)p->nvx * p->nvy;
-    l.bytes_device = 2ull * cells * l.elem + v2 * (8 * 3 + l.elem) + (uint64_t)p->nx * 8 * 6 +
-                     (uint64_t)p->nx * l.n_it * 8 + (uint64_t)l.n_it * 24 + (uint64_t)l.nwg * 8 +
-                     sizeof(DevState) + (uint64_t)p->trace_cap * sizeof(fk_state) + 64;
+    l.bytes_device = 2ull * cells * l.elem + v2 * (8 * 3 + l.elem) + (uint64_t)p->nx * 8 * 7 +
+                     (uint64_t)p->nx * l.n_it_cap * 8 + (uint64_t)l.n_it_cap * 28 + (uint64_t)l.nwg_cap * 8 +
+                     sizeof(DevState) + (uint64_t)p->trace_cap * sizeof(fk_state) + 4096;
     *L = l;
     return FK_OK;
 }

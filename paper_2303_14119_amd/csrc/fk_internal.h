@@ -49,6 +49,7 @@ struct Layout {
     int kc;                      // x planes per tile
     int n_it, n_kc, nwg;
     int n_fast, n_generic;       // v_x tiles taking the fast / generic sweep body
+    int n_it_cap, nwg_cap;       // partial-buffer capacities (any tiling fits)
     size_t lds_sweep, lds_moments;
     uint64_t bytes_device;
 };

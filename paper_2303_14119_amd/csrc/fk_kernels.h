@@ -129,7 +129,6 @@ template <> __device__ __forceinline__ float bload<float>(rsrc_t r, int voff, in
 }
 template <> __device__ __forceinline__ double bload<double>(rsrc_t r, int voff, int soff)
 {
-    typedef int v2i __attribute__((ext_vector_type(2)));
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }
 template <typename T> __device__ __forceinline__ void bstore(T v, rsrc_t r, int voff, int soff);
@@ -155,13 +154,11 @@ template <> __device__ __forceinline__ void bstore<double>(double v, rsrc_t r, i
 // L2 hits: the neighbouring tiles run on the same XCD) and one halo plane per
 // chunk.
 template <typename T, int TI, bool EDGE>
-__device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, int wg, int it, int kci, double* smem)
+__device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, int it, int kci, double* smem, int j, int B)
 {
     const int i0 = it * TI;
     const int k0 = kci * a.kc;
     const int k1 = min(k0 + a.kc, a.nx);
-    const int j = threadIdx.x;
-    const int B = blockDim.x;
     const int nw = B >> 6;
     const int lane = j & 63, wave = j >> 6;
     const bool jok = j < a.nvy;

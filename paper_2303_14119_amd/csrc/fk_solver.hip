@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(MAXB) k_sweep(SweepArgs<T> a)
     extern __shared__ double smem[];
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
     const int it = a.tile_list[wg % a.n_list];
-    sweep_fast_dispatch<T, TI>(a, wg, it, wg / a.n_list, smem);
+    sweep_fast_dispatch<T, TI>(a, it, wg / a.n_list, smem, threadIdx.x, blockDim.x);
 }
 
 template <typename T, int TI, int MAXB>
@@ -129,7 +129,7 @@ __global__ void __launch_bounds__(MAXB) k_sweep_generic(SweepArgs<T> a)
     extern __shared__ double smem[];
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
     const int it = a.tile_list[wg % a.n_list];
-    sweep_body<T, TI, true>(a, wg, it, wg / a.n_list, smem);
+    sweep_body<T, TI, true>(a, it, wg / a.n_list, smem, threadIdx.x, blockDim.x);
 }
 
 template <typename T, int TI>
@@ -181,6 +181,7 @@ struct fk_ctx {
     std::vector<Ev> events;
     std::vector<hipEvent_t> spare;
     std::vector<int> tile_order;   // host copy of the tile list (kept alive for the async upload)
+    bool batch_member = false;     // stepped by a batch, not by fk_step
 };
 
 namespace {
@@ -330,6 +331,20 @@ void enqueue_step(const fk_ctx* c, int from, hipStream_t s)
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
+// v_x tiles of the current layout: fast ones first, then the generic ones
+int upload_tiles(fk_ctx* c)
+{
+    std::vector<int> order;
+    for (int it = 0; it < c->L.n_it; ++it)
+        if (tile_is_fast(it, c->L.ti, c->p.nvx)) order.push_back(it);
+    for (int it = 0; it < c->L.n_it; ++it)
+        if (!tile_is_fast(it, c->L.ti, c->p.nvx)) order.push_back(it);
+    c->tile_order = order;
+    FK_HIP(c, hipMemcpyAsync(c->b.tiles, c->tile_order.data(), order.size() * sizeof(int),
+                             hipMemcpyHostToDevice, c->stream));
+    return FK_OK;
+}
+
 int alloc_buffers(fk_ctx* c, void* fa, void* fb)
 {
     const fk_params& p = c->p;
@@ -339,10 +354,10 @@ int alloc_buffers(fk_ctx* c, void* fa, void* fb)
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
     const size_t o_delta = take(v2 * 8), o_ghat = take(v2 * 8), o_fsrc64 = take(v2 * 8),
                  o_fsrc = take(v2 * L.elem), o_wband = take(p.nx * 8), o_srck = take(p.nx * 8),
-                 o_pn = take((size_t)p.nx * L.n_it * 8), o_pw = take((size_t)L.n_it * 16),
-                 o_pt = take((size_t)L.n_it * 8), o_plv = take((size_t)L.nwg * 8),
+                 o_pn = take((size_t)p.nx * L.n_it_cap * 8), o_pw = take((size_t)L.n_it_cap * 16),
+                 o_pt = take((size_t)L.n_it_cap * 8), o_plv = take((size_t)L.nwg_cap * 8),
                  o_ne = take(p.nx * 8), o_ex = take(p.nx * 8), o_dxk = take(p.nx * 8),
-                 o_consts = take(64), o_tiles = take((size_t)L.n_it * sizeof(int)),
+                 o_consts = take(64), o_tiles = take((size_t)L.n_it_cap * sizeof(int)),
                  o_psum = take((size_t)p.nx * 8), o_wsum = take(4 * 8),
                  o_st = take(sizeof(DevState)),
                  o_ring = take((size_t)p.trace_cap * sizeof(fk_state));
@@ -372,14 +387,8 @@ int alloc_buffers(fk_ctx* c, void* fa, void* fb)
     c->b.ring = (fk_state*)(base + o_ring);
     FK_HIP(c, hipMemsetAsync(c->pool, 0, off, c->stream));
     {
-        std::vector<int> order;
-        for (int it = 0; it < L.n_it; ++it)
-            if (tile_is_fast(it, L.ti, p.nvx)) order.push_back(it);
-        for (int it = 0; it < L.n_it; ++it)
-            if (!tile_is_fast(it, L.ti, p.nvx)) order.push_back(it);
-        c->tile_order = order;
-        FK_HIP(c, hipMemcpyAsync(c->b.tiles, c->tile_order.data(), order.size() * sizeof(int),
-                                 hipMemcpyHostToDevice, c->stream));
+        int rc = upload_tiles(c);
+        if (rc) return rc;
     }
     const size_t fbytes = (size_t)L.cells * L.elem;
     if (fa) {
@@ -450,6 +459,13 @@ int refresh(fk_ctx* c)
 
 int capture_graphs(fk_ctx* c)
 {
+    c->graph_ready = false;
+    for (auto& g : c->graph)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+    if (c->batch_member) return FK_OK;   // a batch replays its own graphs
     c->graph_steps = 16;
     for (int start = 0; start < 2; ++start) {
         hipGraph_t g = nullptr;
@@ -537,7 +553,48 @@ void release(fk_ctx* c)
     delete c;
 }
 
-int create_impl(const fk_params* p, void* stream, void* fa, void* fb, fk_ctx** out)
+// Switch the context to another tiling (v_x rows, x planes per tile); the
+// partial buffers are sized for any tiling.  Recomputes the prologue of the
+// current state and recaptures the step graphs.
+int retile(fk_ctx* c, int ti, int kc)
+{
+    fk_params q = c->p;
+    q.tile_rows = ti;
+    q.tile_planes = kc;
+    Layout L;
+    std::string why;
+    int rc = derive_layout(&q, &L, &why);
+    if (rc) return set_error(&c->err, rc, why);
+    FK_HIP(c, hipStreamSynchronize(c->stream));
+    c->p.tile_rows = ti;
+    c->p.tile_planes = kc;
+    c->L = L;
+    rc = upload_tiles(c);
+    if (!rc) rc = refresh(c);
+    if (!rc) rc = capture_graphs(c);
+    if (!rc) FK_HIP(c, hipStreamSynchronize(c->stream));
+    return rc;
+}
+
+// Candidate tilings of a parameter set (the autotuner's search space).
+std::vector<std::pair<int, int>> tile_candidates(const fk_params& p)
+{
+    std::vector<std::pair<int, int>> out;
+    const int tis[3] = {4, 8, 16};
+    const int kcs[4] = {16, 32, 64, 128};
+    for (int ti : tis)
+        for (int kc : kcs) {
+            fk_params q = p;
+            q.tile_rows = ti;
+            q.tile_planes = kc;
+            Layout L;
+            if (derive_layout(&q, &L, nullptr) == FK_OK && L.kc == kc) out.push_back({ti, kc});
+        }
+    if (out.empty()) out.push_back({0, 0});
+    return out;
+}
+
+int create_impl(const fk_params* p, void* stream, void* fa, void* fb, fk_ctx** out, bool member = false)
 {
     if (!out) return set_error(nullptr, FK_E_INVALID, "out is NULL");
     *out = nullptr;
@@ -552,8 +609,9 @@ int create_impl(const fk_params* p, void* stream, void* fa, void* fb, fk_ctx** o
     c->p = *p;
     c->L = L;
     c->stream = static_cast<hipStream_t>(stream);
+    c->batch_member = member;
     hipError_t e = hipGetDevice(&c->device);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+    if (e == hipSuccess && !member) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         std::string m = std::string("HIP initialisation failed: ") + hipGetErrorString(e);
         release(c);
@@ -611,6 +669,7 @@ extern "C" int fk_query(const fk_ctx* c, fk_info* out)
 extern "C" int fk_step(fk_ctx* c, int64_t n)
 {
     if (!c || n < 0) return set_error(c ? &c->err : nullptr, FK_E_INVALID, "bad arguments to fk_step");
+    if (c->batch_member) return set_error(&c->err, FK_E_STATE, "a batch member is stepped through fk_batch_step");
     if (c->sticky) return c->sticky;
     if (c->prof) {
         // two events per step, around the sweep launch only; the interval
@@ -793,3 +852,476 @@ extern "C" int fk_kernel_times(fk_ctx* c, double* sweep_ms, int64_t* sweep_n, do
     if (field_n) *field_n = n[1];
     return FK_OK;
 }
+
+extern "C" int fk_autotune(fk_ctx* c, int trial_steps, fk_info* chosen)
+{
+    if (!c || trial_steps < 2) return FK_E_INVALID;
+    if (c->batch_member) return set_error(&c->err, FK_E_STATE, "batch members are tuned by their batch");
+    if (c->sticky) return c->sticky;
+    const bool prof = c->prof;
+    c->prof = false;
+    size_t begin = 0;
+    int rc = drain(c, &begin);
+    if (rc && rc != FK_E_STATE) return rc;
+    DevState saved;
+    rc = read_devstate(c, &saved);
+    if (rc) return rc;
+    // keep the state while the trials step it
+    const size_t fbytes = (size_t)c->L.cells * c->L.elem;
+    void* keep = nullptr;
+    std::vector<char> host_keep;
+    if (hipMalloc(&keep, fbytes) == hipSuccess) {
+        FK_HIP(c, hipMemcpyAsync(keep, c->b.f[c->cur], fbytes, hipMemcpyDeviceToDevice, c->stream));
+    } else {
+        keep = nullptr;
+        host_keep.resize(fbytes);
+        FK_HIP(c, hipMemcpyAsync(host_keep.data(), c->b.f[c->cur], fbytes, hipMemcpyDeviceToHost, c->stream));
+    }
+    hipEvent_t e0 = get_event(c), e1 = get_event(c);
+    if (!e0 || !e1) rc = set_error(&c->err, FK_E_HIP, "hipEventCreate failed");
+    int best_ti = c->L.ti, best_kc = c->L.kc;
+    float best_ms = 1e30f;
+    for (auto cand : tile_candidates(c->p)) {
+        if (rc) break;
+        rc = retile(c, cand.first, cand.second);
+        if (rc) break;
+        rc = fk_step(c, 2);
+        if (rc) break;
+        if (hipEventRecord(e0, c->stream) != hipSuccess) { rc = FK_E_HIP; break; }
+        rc = fk_step(c, trial_steps);
+        if (rc) break;
+        if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { rc = FK_E_HIP; break; }
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = FK_E_HIP; break; }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best_ti = c->L.ti;
+            best_kc = c->L.kc;
+        }
+    }
+    if (e0) c->spare.push_back(e0);
+    if (e1) c->spare.push_back(e1);
+    if (!rc) rc = retile(c, best_ti, best_kc);
+    // restore the state
+    if (keep) {
+        if (hipMemcpyAsync(c->b.f[c->cur], keep, fbytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess && !rc)
+            rc = FK_E_HIP;
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(keep);
+    } else if (hipMemcpyAsync(c->b.f[c->cur], host_keep.data(), fbytes, hipMemcpyHostToDevice, c->stream) != hipSuccess && !rc) {
+        rc = FK_E_HIP;
+    }
+    if (hipMemcpyAsync(c->b.st, &saved, sizeof(saved), hipMemcpyHostToDevice, c->stream) != hipSuccess && !rc) rc = FK_E_HIP;
+    if (!rc) rc = refresh(c);
+    if (!rc) FK_HIP(c, hipStreamSynchronize(c->stream));
+    c->prof = prof;
+    if (rc) return rc;
+    if (chosen) return fk_query(c, chosen);
+    return FK_OK;
+}
+
+// ================================================================ batch
+//
+// Independent instances of uneven sizes advanced together: one persistent
+// sweep launch per step pulls (instance, x chunk, group of v_x tiles) work
+// items from an atomic counter, largest first; a workgroup of 256 threads
+// runs 256 / block tiles of one item side by side.  The reductions and field
+// solves of all instances follow as one launch each.  The three launches of
+// a step are replayed from captured HIP graphs.
+
+namespace fk {
+
+constexpr int kBatchThreads = 256;
+
+struct BatchInst {
+    SweepArgs<float> sw[2];   // from buffer 0 / from buffer 1
+    ReduceArgs rd;
+    FieldArgs fd;
+    int block, group, kc, nx, lds_doubles;
+};
+
+struct BatchItem {
+    int inst, it0, ntiles, kci;
+};
+
+// sched 0: items taken from an atomic counter (dynamic); sched 1: workgroup
+// w takes items w, w + grid, ... of the cost-sorted list (static).
+template <int TI>
+__global__ void __launch_bounds__(kBatchThreads) k_batch_sweep(const BatchInst* __restrict__ insts,
+                                                               const BatchItem* __restrict__ items,
+                                                               int n_items, int* __restrict__ counter, int from,
+                                                               int sched)
+{
+    extern __shared__ double smem[];
+    __shared__ int next;
+    for (int round = 0;; ++round) {
+        if (sched == 0) {
+            if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+            __syncthreads();
+        }
+        const int m = sched == 0 ? __builtin_amdgcn_readfirstlane(next) : (int)blockIdx.x + round * (int)gridDim.x;
+        __syncthreads();
+        if (m >= n_items) break;
+        const BatchItem item = items[m];
+        const BatchInst* in = insts + item.inst;
+        const int B = in->block;
+        const int sub = threadIdx.x / B;
+        const int j = threadIdx.x - sub * B;
+        const int k0 = item.kci * in->kc;
+        const int np = min(in->kc, in->nx - k0);
+        if (sub < item.ntiles)
+            sweep_any<float, TI>(in->sw[from], item.it0 + sub, item.kci, smem + (size_t)sub * in->lds_doubles, j, B);
+        else
+            sweep_idle(np);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_batch_reduce(const BatchInst* __restrict__ insts)
+{
+    __shared__ double sh[256];
+    reduce_tiles(insts[blockIdx.y].rd, sh);
+}
+
+__global__ void __launch_bounds__(kFieldThreads) k_batch_field(const BatchInst* __restrict__ insts, int* counter, int advance)
+{
+    __shared__ double sh[2 * kFieldThreads];
+    FieldArgs a = insts[blockIdx.x].fd;
+    a.advance = advance;
+    field_block(a, sh);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;   // the sweep of this step has finished
+}
+
+}  // namespace fk
+
+struct fk_batch {
+    std::vector<fk_ctx*> inst;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    int ti = 8;
+    int sched = 0;                // 0 dynamic (atomic counter), 1 static round-robin
+    int grid = 0;
+    size_t lds = 0;
+    int max_blocks_x = 1;
+    std::vector<BatchInst> inst_host;
+    std::vector<BatchItem> items_host;
+    BatchInst* d_inst = nullptr;
+    BatchItem* d_items = nullptr;
+    int* d_counter = nullptr;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    int graph_steps = 8;
+    int cur = 0;
+    int sticky = FK_OK;
+    std::string err;
+};
+
+namespace {
+
+int bfail(fk_batch* b, hipError_t e, const char* what)
+{
+    return set_error(&b->err, FK_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define FK_BHIP(b, call)                                     \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return bfail((b), e_, #call);  \
+    } while (0)
+
+size_t batch_slice_doubles(int ti, int block, int kc)
+{
+    const int waves = block / 64;
+    const size_t bytes = (size_t)2 * ti * (block + 2) * 4 + (size_t)kc * waves * 8 + (size_t)waves * 32;
+    return (bytes + 7) / 8;
+}
+
+void batch_launch_step(const fk_batch* b, int from, hipStream_t s)
+{
+    const size_t n_items = b->items_host.size();
+    if (b->ti == 4)
+        hipLaunchKernelGGL(k_batch_sweep<4>, dim3(b->grid), dim3(kBatchThreads), b->lds, s, b->d_inst, b->d_items,
+                           (int)n_items, b->d_counter, from, b->sched);
+    else
+        hipLaunchKernelGGL(k_batch_sweep<8>, dim3(b->grid), dim3(kBatchThreads), b->lds, s, b->d_inst, b->d_items,
+                           (int)n_items, b->d_counter, from, b->sched);
+    hipLaunchKernelGGL(k_batch_reduce, dim3(b->max_blocks_x, b->inst.size()), dim3(256), 0, s, b->d_inst);
+    hipLaunchKernelGGL(k_batch_field, dim3(b->inst.size()), dim3(kFieldThreads), 0, s, b->d_inst, b->d_counter, 1);
+}
+
+// (Re)build the instance descriptors and the work list for the members'
+// current tiling, and capture the step graphs.
+int batch_build(fk_batch* b, int wgs_per_cu)
+{
+    FK_BHIP(b, hipStreamSynchronize(b->stream));
+    b->inst_host.clear();
+    b->items_host.clear();
+    b->lds = 0;
+    b->max_blocks_x = 1;
+    for (size_t m = 0; m < b->inst.size(); ++m) {
+        fk_ctx* c = b->inst[m];
+        BatchInst d{};
+        d.sw[0] = sweep_args<float>(c, 0);
+        d.sw[1] = sweep_args<float>(c, 1);
+        d.rd.part_n = c->b.part_n;
+        d.rd.part_wall = c->b.part_wall;
+        d.rd.part_top = c->b.part_top;
+        d.rd.part_lv = c->b.part_lv;
+        d.rd.plane_sum = c->b.plane_sum;
+        d.rd.wall_sum = c->b.wall_sum;
+        d.rd.nx = c->p.nx;
+        d.rd.n_it = c->L.n_it;
+        d.rd.nwg = c->L.nwg;
+        d.fd = field_args(c, 1);
+        d.block = c->L.block;
+        d.group = kBatchThreads / c->L.block;
+        d.kc = c->L.kc;
+        d.nx = c->p.nx;
+        d.lds_doubles = (int)batch_slice_doubles(b->ti, c->L.block, c->L.kc);
+        b->lds = std::max(b->lds, (size_t)d.group * d.lds_doubles * 8);
+        b->max_blocks_x = std::max(b->max_blocks_x, (c->p.nx + 255) / 256);
+        b->inst_host.push_back(d);
+        for (int kci = 0; kci < c->L.n_kc; ++kci)
+            for (int it0 = 0; it0 < c->L.n_it; it0 += d.group)
+                b->items_host.push_back({(int)m, it0, std::min(d.group, c->L.n_it - it0), kci});
+    }
+    // largest items first
+    std::stable_sort(b->items_host.begin(), b->items_host.end(), [&](const BatchItem& x, const BatchItem& y) {
+        auto cost = [&](const BatchItem& t) {
+            const fk_ctx* c = b->inst[t.inst];
+            const int np = std::min(c->L.kc, c->p.nx - t.kci * c->L.kc);
+            return (double)t.ntiles * np * c->p.nvy;
+        };
+        return cost(x) > cost(y);
+    });
+    if (b->d_inst) (void)hipFree(b->d_inst);
+    if (b->d_items) (void)hipFree(b->d_items);
+    b->d_inst = nullptr;
+    b->d_items = nullptr;
+    FK_BHIP(b, hipMalloc(&b->d_inst, sizeof(BatchInst) * b->inst_host.size()));
+    FK_BHIP(b, hipMalloc(&b->d_items, sizeof(BatchItem) * b->items_host.size()));
+    FK_BHIP(b, hipMemcpy(b->d_inst, b->inst_host.data(), sizeof(BatchInst) * b->inst_host.size(), hipMemcpyHostToDevice));
+    FK_BHIP(b, hipMemcpy(b->d_items, b->items_host.data(), sizeof(BatchItem) * b->items_host.size(), hipMemcpyHostToDevice));
+    // persistent grid: every compute unit holds wgs_per_cu workgroups
+    int dev = 0, cus = 0, occ = 0;
+    FK_BHIP(b, hipGetDevice(&dev));
+    FK_BHIP(b, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    if (b->ti == 4)
+        FK_BHIP(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_sweep<4>, kBatchThreads, b->lds));
+    else
+        FK_BHIP(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_sweep<8>, kBatchThreads, b->lds));
+    if (occ < 1) return set_error(&b->err, FK_E_INVALID, "batch tiles need more LDS than a compute unit has");
+    const int per_cu = wgs_per_cu > 0 ? std::min(wgs_per_cu, occ) : occ;
+    b->grid = cus * per_cu;
+    // graphs of graph_steps steps from either buffer
+    for (auto& g : b->graph)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+    for (int start = 0; start < 2; ++start) {
+        hipGraph_t g = nullptr;
+        FK_BHIP(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeRelaxed));
+        for (int s = 0; s < b->graph_steps; ++s) batch_launch_step(b, (start + s) & 1, b->cap_stream);
+        hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+        if (e != hipSuccess) return bfail(b, e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&b->graph[start], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return bfail(b, e, "hipGraphInstantiate");
+    }
+    return FK_OK;
+}
+
+void batch_release(fk_batch* b)
+{
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    for (auto& g : b->graph)
+        if (g) (void)hipGraphExecDestroy(g);
+    for (auto c : b->inst) release(c);
+    if (b->d_inst) (void)hipFree(b->d_inst);
+    if (b->d_items) (void)hipFree(b->d_items);
+    if (b->d_counter) (void)hipFree(b->d_counter);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    delete b;
+}
+
+int batch_steps(fk_batch* b, int64_t n)
+{
+    int64_t left = n;
+    while (left >= b->graph_steps) {
+        FK_BHIP(b, hipGraphLaunch(b->graph[b->cur], b->stream));
+        left -= b->graph_steps;
+    }
+    for (; left > 0; --left) {
+        batch_launch_step(b, b->cur, b->stream);
+        b->cur ^= 1;
+    }
+    FK_BHIP(b, hipGetLastError());
+    for (auto c : b->inst) c->cur = b->cur;
+    return FK_OK;
+}
+
+// zero f and the scalars of every member
+int batch_reset(fk_batch* b)
+{
+    for (auto c : b->inst) {
+        const size_t fbytes = (size_t)c->L.cells * c->L.elem;
+        FK_BHIP(b, hipMemsetAsync(c->b.f[0], 0, fbytes, b->stream));
+        FK_BHIP(b, hipMemsetAsync(c->b.f[1], 0, fbytes, b->stream));
+        FK_BHIP(b, hipMemsetAsync(c->b.st, 0, sizeof(DevState), b->stream));
+        c->history.clear();
+        c->drained_step = -1;
+        c->sticky = FK_OK;
+        if (refresh(c)) return set_error(&b->err, FK_E_HIP, c->err);
+    }
+    FK_BHIP(b, hipStreamSynchronize(b->stream));
+    return FK_OK;
+}
+
+}  // namespace
+
+extern "C" int fk_batch_create(const fk_params* params, int n, void* stream, int autotune, fk_batch** out)
+{
+    if (!out || !params || n < 1) return set_error(nullptr, FK_E_INVALID, "bad arguments to fk_batch_create");
+    *out = nullptr;
+    for (int m = 0; m < n; ++m) {
+        Layout L;
+        std::string why;
+        int rc = derive_layout(&params[m], &L, &why);
+        if (rc) return set_error(nullptr, rc, "instance " + std::to_string(m) + ": " + why);
+        if (params[m].dtype != FK_F32) return set_error(nullptr, FK_E_INVALID, "batched instances are FK_F32");
+        if (L.block > kBatchThreads) return set_error(nullptr, FK_E_INVALID, "batched instances need nvy <= 256");
+    }
+    fk_batch* b = new (std::nothrow) fk_batch();
+    if (!b) return set_error(nullptr, FK_E_OOM, "host allocation failed");
+    b->stream = static_cast<hipStream_t>(stream);
+    int rc = FK_OK;
+    if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) rc = FK_E_HIP;
+    if (!rc && hipMalloc(&b->d_counter, sizeof(int)) != hipSuccess) rc = FK_E_OOM;
+    if (!rc && hipMemset(b->d_counter, 0, sizeof(int)) != hipSuccess) rc = FK_E_HIP;
+    for (int m = 0; m < n && !rc; ++m) {
+        fk_params q = params[m];
+        q.tile_rows = b->ti;
+        if (q.tile_planes == 0) q.tile_planes = 32;
+        fk_ctx* c = nullptr;
+        rc = create_impl(&q, stream, nullptr, nullptr, &c, true);
+        if (!rc) b->inst.push_back(c);
+    }
+    if (!rc) rc = batch_build(b, 0);
+    if (!rc && autotune) {
+        // search the tiling (rows, planes) and the persistent grid size on a
+        // short run, then start the instances again from f = 0
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = FK_E_HIP;
+        int best_ti = 8, best_kc = 32, best_occ = 0, best_sched = 0;
+        float best_ms = 1e30f;
+        const int tis[2] = {4, 8};
+        const int kcs[3] = {16, 32, 64};
+        const int occs[3] = {2, 3, 0};
+        for (int ti : tis)
+            for (int kc : kcs)
+                for (int occ : occs)
+                for (int sched = 0; sched < 2; ++sched) {
+                    if (rc) break;
+                    b->ti = ti;
+                    b->sched = sched;
+                    for (auto c : b->inst) {
+                        const int kcc = std::min(kc, c->p.nx);
+                        if (!rc) rc = retile(c, ti, kcc < 4 ? 0 : kcc);
+                    }
+                    if (!rc) rc = batch_build(b, occ);
+                    if (!rc) rc = batch_steps(b, 2);
+                    if (rc) break;
+                    (void)hipEventRecord(e0, b->stream);
+                    rc = batch_steps(b, 16);
+                    (void)hipEventRecord(e1, b->stream);
+                    if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = FK_E_HIP;
+                    float ms = 0;
+                    if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = FK_E_HIP;
+                    if (!rc && ms < best_ms) {
+                        best_ms = ms;
+                        best_ti = ti;
+                        best_kc = kc;
+                        best_occ = occ;
+                        best_sched = sched;
+                    }
+                }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (!rc) {
+            b->ti = best_ti;
+            b->sched = best_sched;
+            for (auto c : b->inst) {
+                const int kcc = std::min(best_kc, c->p.nx);
+                if (!rc) rc = retile(c, best_ti, kcc < 4 ? 0 : kcc);
+            }
+            if (!rc) rc = batch_build(b, best_occ);
+            if (!rc) rc = batch_reset(b);
+            b->cur = 0;
+            for (auto c : b->inst) c->cur = 0;
+        }
+    }
+    if (rc) {
+        std::string m = b->err;
+        for (auto c : b->inst)
+            if (!c->err.empty()) m += " / " + c->err;
+        batch_release(b);
+        return set_error(nullptr, rc, m.empty() ? std::string("batch creation failed") : m);
+    }
+    *out = b;
+    return FK_OK;
+}
+
+extern "C" int fk_batch_destroy(fk_batch* b)
+{
+    if (!b) return FK_E_INVALID;
+    batch_release(b);
+    return FK_OK;
+}
+
+extern "C" int fk_batch_step(fk_batch* b, int64_t n)
+{
+    if (!b || n < 0) return FK_E_INVALID;
+    if (b->sticky) return b->sticky;
+    return batch_steps(b, n);
+}
+
+extern "C" int fk_batch_sync(fk_batch* b, int* first_bad)
+{
+    if (!b) return FK_E_INVALID;
+    FK_BHIP(b, hipStreamSynchronize(b->stream));
+    if (first_bad) *first_bad = -1;
+    for (size_t m = 0; m < b->inst.size(); ++m) {
+        int rc = fk_sync(b->inst[m]);
+        if (rc) {
+            b->sticky = rc;
+            if (first_bad) *first_bad = (int)m;
+            return set_error(&b->err, rc, "instance " + std::to_string(m) + ": " + b->inst[m]->err);
+        }
+    }
+    return FK_OK;
+}
+
+extern "C" int fk_batch_get(fk_batch* b, int i, fk_ctx** view)
+{
+    if (!b || !view || i < 0 || i >= (int)b->inst.size()) return FK_E_INVALID;
+    *view = b->inst[i];
+    return FK_OK;
+}
+
+extern "C" int fk_batch_info(const fk_batch* b, fk_batch_info_t* out)
+{
+    if (!b || !out) return FK_E_INVALID;
+    out->n = (int)b->inst.size();
+    out->tile_rows = b->ti;
+    out->grid = b->grid;
+    out->items = (int)b->items_host.size();
+    out->lds_bytes = (int64_t)b->lds;
+    int64_t cells = 0;
+    for (auto c : b->inst) cells += c->L.cells;
+    out->cells = cells;
+    out->tile_planes = b->inst.empty() ? 0 : b->inst[0]->L.kc;
+    out->schedule = b->sched;
+    return FK_OK;
+}
+
+extern "C" const char* fk_batch_last_error(const fk_batch* b) { return b ? b->err.c_str() : global_error(); }

@@ -17,13 +17,11 @@
 namespace fk {
 
 template <typename T, int TI, int S>
-__device__ __forceinline__ void sweep_fast(const SweepArgs<T>& a, int wg, int it, int kci, double* smem)
+__device__ __forceinline__ void sweep_fast(const SweepArgs<T>& a, int it, int kci, double* smem, int j, int B)
 {
     const int i0 = it * TI;
     const int k0 = kci * a.kc;
     const int k1 = min(k0 + a.kc, a.nx);
-    const int j = threadIdx.x;
-    const int B = blockDim.x;
     const int nw = B >> 6;
     const int lane = j & 63, wave = j >> 6;
     const bool jok = j < a.nvy;
@@ -230,18 +228,34 @@ __device__ __forceinline__ void sweep_fast(const SweepArgs<T>& a, int wg, int it
         }
         if (k1 == a.nx) a.part_top[it] = t3;
     }
-    (void)wg;
 }
 
 template <typename T, int TI>
-__device__ __forceinline__ void sweep_fast_dispatch(const SweepArgs<T>& a, int wg, int it, int kci, double* smem)
+__device__ __forceinline__ void sweep_fast_dispatch(const SweepArgs<T>& a, int it, int kci, double* smem, int j, int B)
 {
     switch (tile_split(it, TI, a.nvx)) {
-    case 0: sweep_fast<T, TI, 0>(a, wg, it, kci, smem); break;
-    case 1: sweep_fast<T, TI, 1>(a, wg, it, kci, smem); break;
-    case TI + 1: sweep_fast<T, TI, TI + 1>(a, wg, it, kci, smem); break;
-    default: sweep_fast<T, TI, TI + 2>(a, wg, it, kci, smem); break;
+    case 0: sweep_fast<T, TI, 0>(a, it, kci, smem, j, B); break;
+    case 1: sweep_fast<T, TI, 1>(a, it, kci, smem, j, B); break;
+    case TI + 1: sweep_fast<T, TI, TI + 1>(a, it, kci, smem, j, B); break;
+    default: sweep_fast<T, TI, TI + 2>(a, it, kci, smem, j, B); break;
     }
+}
+
+// Any tile: the fast body when the tile qualifies, else the generic one.
+template <typename T, int TI>
+__device__ __forceinline__ void sweep_any(const SweepArgs<T>& a, int it, int kci, double* smem, int j, int B)
+{
+    if (tile_is_fast(it, TI, a.nvx)) sweep_fast_dispatch<T, TI>(a, it, kci, smem, j, B);
+    else sweep_body<T, TI, true>(a, it, kci, smem, j, B);
+}
+
+// A sub-tile slot of a batched workgroup with no tile: take part in the same
+// number of workgroup barriers as a tile of nplanes x planes.
+__device__ __forceinline__ void sweep_idle(int nplanes)
+{
+    for (int k = 0; k < nplanes; ++k) __syncthreads();
+    __syncthreads();
+    __syncthreads();
 }
 
 }  // namespace fk

@@ -63,6 +63,17 @@ class fk_info(C.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+class fk_batch_info_t(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32), ("tile_rows", C.c_int32), ("tile_planes", C.c_int32),
+        ("grid", C.c_int32), ("items", C.c_int32), ("lds_bytes", C.c_int64), ("cells", C.c_int64),
+        ("schedule", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
 _P = C.POINTER
 _vp = C.c_void_p
 _ctx = C.c_void_p
@@ -86,6 +97,14 @@ SIGNATURES = {
     "fk_saturation_check": (C.c_int, [_P(fk_state), C.c_size_t, C.c_double, C.c_double, _P(C.c_int)]),
     "fk_set_profiling": (C.c_int, [_ctx, C.c_int]),
     "fk_kernel_times": (C.c_int, [_ctx, _P(C.c_double), _P(C.c_int64), _P(C.c_double), _P(C.c_int64)]),
+    "fk_autotune": (C.c_int, [_ctx, C.c_int, _P(fk_info)]),
+    "fk_batch_create": (C.c_int, [_P(fk_params), C.c_int, _vp, C.c_int, _P(_vp)]),
+    "fk_batch_destroy": (C.c_int, [_vp]),
+    "fk_batch_step": (C.c_int, [_vp, C.c_int64]),
+    "fk_batch_sync": (C.c_int, [_vp, _P(C.c_int)]),
+    "fk_batch_get": (C.c_int, [_vp, C.c_int, _P(_ctx)]),
+    "fk_batch_info": (C.c_int, [_vp, _P(fk_batch_info_t)]),
+    "fk_batch_last_error": (C.c_char_p, [_vp]),
 }
 for _name, (_res, _args) in SIGNATURES.items():
     _fn = getattr(_lib, _name)
@@ -236,8 +255,88 @@ class Solver:
     def set_profiling(self, on=True):
         self._chk(fk_set_profiling(self._h, 1 if on else 0))
 
+    def autotune(self, trial_steps=16):
+        info = fk_info()
+        self._chk(fk_autotune(self._h, int(trial_steps), C.byref(info)))
+        self.info = info.as_dict()
+        return self.info
+
     def kernel_times(self):
         a, b = C.c_double(), C.c_double()
         na, nb = C.c_int64(), C.c_int64()
         self._chk(fk_kernel_times(self._h, C.byref(a), C.byref(na), C.byref(b), C.byref(nb)))
         return dict(sweep_ms=a.value, sweep_n=na.value, field_ms=b.value, field_n=nb.value)
+
+
+class View(Solver):
+    """Non-owning handle of one instance of a Batch (read and write state)."""
+
+    def __init__(self, handle, cfg, dtype):
+        self._h = handle
+        self.params = make_params(cfg, dtype)
+        self.np_dtype = np.float32
+        info = fk_info()
+        check(fk_query(self._h, C.byref(info)), self._h)
+        self.info = info.as_dict()
+        self.shape = (cfg["nx"], cfg["nvx"], cfg["nvy"])
+        self.dt = self.info["dt"]
+
+    def close(self):
+        self._h = None
+
+
+class Batch:
+    """Independent FP32 instances stepped together by one persistent launch
+    per step (fk_batch_*)."""
+
+    def __init__(self, cfgs, stream=None, autotune=False, **kw):
+        self.cfgs = list(cfgs)
+        arr = (fk_params * len(self.cfgs))(*[make_params(c, "f32", **kw) for c in self.cfgs])
+        h = _vp()
+        rc = fk_batch_create(arr, len(self.cfgs), stream, 1 if autotune else 0, C.byref(h))
+        if rc != OK:
+            raise FlashkinError(rc, (fk_batch_last_error(None) or b"").decode())
+        self._h = h
+        self.views = []
+        for i, c in enumerate(self.cfgs):
+            v = _ctx()
+            self._chk(fk_batch_get(self._h, i, C.byref(v)))
+            self.views.append(View(v, c, "f32"))
+
+    def _chk(self, rc):
+        if rc != OK:
+            raise FlashkinError(rc, (fk_batch_last_error(self._h) or b"").decode())
+        return rc
+
+    def step(self, n=1):
+        self._chk(fk_batch_step(self._h, int(n)))
+
+    def sync(self):
+        bad = C.c_int(-1)
+        rc = fk_batch_sync(self._h, C.byref(bad))
+        if rc != OK:
+            raise FlashkinError(rc, (fk_batch_last_error(self._h) or b"").decode())
+
+    def info(self):
+        out = fk_batch_info_t()
+        self._chk(fk_batch_info(self._h, C.byref(out)))
+        return out.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            for v in self.views:
+                v.close()
+            fk_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,124 @@
+"""Batched instances (one persistent sweep launch per step) and the tiling
+autotuner, on the GPU: every instance against the FP64 oracle, and bitwise
+against a standalone context with the same tiling."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle.solver import Oracle, set_threads
+from paper_2303_14119_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+set_threads(min(16, os.cpu_count() or 1))
+
+
+@pytest.fixture(scope="module")
+def fk():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2303_14119_amd import flashkin
+    return flashkin
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def small_instances(seed, n):
+    """Uneven instances drawn like the batched sweep, at sizes the oracle runs
+    quickly: odd and even velocity grids, ragged tiles, 1..4 tiles per group."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        nx = int(rng.integers(20, 140))
+        nv = int(rng.integers(20, 200))
+        out.append(W.config(nx=nx, nvx=nv, nvy=nv, length=float(rng.uniform(0.1e-3, 1e-3)),
+                            ey=-float(rng.uniform(1e6, 10e6)), delta_max=float(rng.uniform(1.5, 3.5)),
+                            a_max_ev=float(rng.uniform(250, 600)), t_se_ev=float(rng.uniform(1, 5)),
+                            j_src=1e5))
+    return out
+
+
+@pytest.mark.parametrize("autotune", [False, True])
+def test_batch_members_match_oracle(fk, autotune):
+    cfgs = small_instances(5, 7)
+    steps = 60
+    with fk.Batch(cfgs, autotune=autotune) as b:
+        info = b.info()
+        assert info["n"] == 7 and info["items"] > 0
+        for m, (c, v) in enumerate(zip(cfgs, b.views)):
+            f0 = W.random_state((c["nx"], c["nvx"], c["nvy"]), seed=m, scale=1e1).astype(np.float32)
+            v.write_state(f0, 1e-6 * m, 0.0, 0)
+        b.step(steps)
+        b.sync()
+        for m, (c, v) in enumerate(zip(cfgs, b.views)):
+            o = Oracle(c)
+            f0 = W.random_state((c["nx"], c["nvx"], c["nvy"]), seed=m, scale=1e1).astype(np.float32)
+            o.set_state(f0.astype(np.float64), 1e-6 * m, 0)
+            o.step(steps)
+            st, orc = v.state(), o.record()
+            assert st["step"] == steps
+            assert rel_l2(v.f(), o.f()) < 1e-5, m
+            for q in ("g_pe", "g_see", "n_total"):
+                assert abs(st[q] - orc[q]) <= 1e-5 * abs(orc[q]) + 1e-30, (m, q)
+            s = st["sigma"] + st["sigma_lo"]
+            assert abs(s - orc["sigma"]) <= 1e-5 * abs(orc["sigma"]) + 1e-30, m
+
+
+def test_batch_is_bitwise_a_standalone_context(fk):
+    cfgs = small_instances(9, 5)
+    with fk.Batch(cfgs, tile_planes=16) as b:
+        b.step(45)
+        b.sync()
+        outs = [(v.f(), v.state()) for v in b.views]
+        ti = b.info()["tile_rows"]
+    for c, (fb, sb) in zip(cfgs, outs):
+        with fk.Solver(c, "f32", tile_rows=ti, tile_planes=min(16, c["nx"])) as s:
+            s.step(45)
+            assert np.array_equal(s.f(), fb)
+            ss = s.state()
+            for q in ("sigma", "sigma_lo", "g_pe", "g_see", "n_total"):
+                assert ss[q] == sb[q], q
+
+
+def test_batch_views_refuse_single_steps(fk):
+    with fk.Batch(small_instances(3, 2)) as b:
+        with pytest.raises(fk.FlashkinError) as ei:
+            b.views[0].step(1)
+        assert ei.value.code == fk.E_STATE
+
+
+def test_autotune_keeps_state_and_results(fk):
+    cfg = W.c0()
+    with fk.Solver(cfg, "f32") as a:
+        a.step(120)
+        before = a.f()
+        st = a.state()
+        chosen = a.autotune(8)
+        assert chosen["tile_rows"] in (4, 8, 16)
+        assert np.array_equal(a.f(), before)
+        st2 = a.state()
+        for q in ("step", "sigma", "sigma_lo", "g_pe", "n_total"):
+            assert st2[q] == st[q], q
+        a.step(80)
+        tuned = a.f()
+    o = Oracle(cfg)
+    o.step(200)
+    assert rel_l2(tuned, o.f()) < 1e-5
+
+
+def test_c2_sweep_workload_runs(fk):
+    """The 64-instance sweep (7e8 cells): a short run, finite and conserving."""
+    cfgs = W.c2_instances(seed=0, n=64)
+    with fk.Batch(cfgs, autotune=True) as b:
+        b.step(50)
+        b.sync()
+        for v in b.views[::9]:
+            st = v.state()
+            assert np.isfinite(st["n_total"]) and st["n_total"] > 0
+            assert abs(st["resid"]) <= 1e-5 * st["n_total"]
