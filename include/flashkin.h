@@ -256,6 +256,42 @@ int fk_batch_get(fk_batch* batch, int i, fk_ctx** view);
 int fk_batch_info(const fk_batch* batch, fk_batch_info_t* out);
 const char* fk_batch_last_error(const fk_batch* batch);
 
+/* ---- surrogate network ---------------------------------------------------
+ * A multilayer perceptron (GELU hidden layers, linear output) that maps the
+ * run parameters to the saturated state; a project addition beyond the
+ * paper.  Trained on the GPU: BF16 MFMA GEMMs with FP32 accumulation, FP32
+ * master weights, MSE loss, AdamW.  The library owns the network's device
+ * memory; inputs and targets are FP32 device arrays given by the caller.
+ * Parameters are exchanged as one flat FP32 vector
+ * [W_1 (dims[1] x dims[0], row-major), b_1, W_2, b_2, ...]. */
+typedef struct fk_mlp fk_mlp;
+
+/* n_layers weight layers, widths dims[0..n_layers]; max_batch a multiple of
+ * 16.  Parameters start at zero (set them with fk_mlp_set_params). */
+int fk_mlp_create(int n_layers, const int32_t* dims, int max_batch, void* stream, fk_mlp** out);
+int fk_mlp_destroy(fk_mlp* net);
+const char* fk_mlp_last_error(const fk_mlp* net);
+int fk_mlp_num_params(const fk_mlp* net, int64_t* count);
+int fk_mlp_set_params(fk_mlp* net, const float* src, int src_on_device);
+int fk_mlp_get_params(fk_mlp* net, float* dst, int dst_on_device);
+/* Gradients of the last fk_mlp_backward, same flat layout. */
+int fk_mlp_get_grads(fk_mlp* net, float* dst, int dst_on_device);
+
+/* x: device FP32 [M][dims[0]]; y (device FP32 [M][dims[n_layers]], may be
+ * NULL).  Keeps the activations for a following fk_mlp_backward. */
+int fk_mlp_forward(fk_mlp* net, const float* x, int M, float* y);
+
+/* Mean-squared-error loss against target (device FP32 [M][dims[n_layers]])
+ * for the batch of the last forward (M a multiple of 16); computes every
+ * parameter gradient.  *loss (host, may be NULL) receives the loss. */
+int fk_mlp_backward(fk_mlp* net, const float* target, int M, float* loss);
+
+/* One AdamW step (decoupled weight decay on the weights, none on biases)
+ * with bias-corrected moments; step counts from 1. */
+int fk_mlp_adamw(fk_mlp* net, double lr, double beta1, double beta2, double eps, double weight_decay,
+                 int64_t step);
+int fk_mlp_sync(fk_mlp* net);
+
 #ifdef __cplusplus
 }
 #endif

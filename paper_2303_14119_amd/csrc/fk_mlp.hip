@@ -1,0 +1,524 @@
+// fk_mlp.hip -- the surrogate network: a multilayer perceptron with GELU
+// hidden layers, trained on the GPU by hand-written BF16 MFMA GEMMs with FP32
+// accumulation, fused bias / GELU / GELU' epilogues, an MSE loss kernel,
+// bias-gradient reductions and an AdamW step on FP32 master weights.
+//
+// Every product is an "NT" GEMM, C[M][N] = A[M][K] * B[N][K]^T with both
+// operands K-contiguous, so the operands of the three passes are stored in
+// the layout they are read in:
+//   forward   Z_l  = A_{l-1} W_l^T          A_{l-1} [M][K], W_l [N][K]
+//   dgrad     dA_l = dZ_{l+1} (W_{l+1}^T)^T   dZ [M][N'], Wt_{l+1} [N][N'] (W transposed)
+//   wgrad     dW_l = dZ_l^T (A_{l-1}^T)^T     dZt [N][M], At_{l-1} [K][M]
+// The epilogues write activations and gradients in both layouts.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fk_internal.h"
+
+namespace fk {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kMaxLayers = 8;
+
+enum GemmEpilogue {
+    EPI_HIDDEN = 0,   // z = acc + b; store z (FP32), gelu(z) as bf16 [M][N] and [N][M]
+    EPI_OUTPUT = 1,   // y = acc + b (FP32)
+    EPI_DGRAD = 2,    // dz = acc * gelu'(z); store bf16 [M][N] and [N][M]
+    EPI_WGRAD = 3     // dW = acc (FP32)
+};
+
+struct GemmArgs {
+    const __bf16* __restrict__ A;
+    const __bf16* __restrict__ B;
+    int lda, ldb;
+    int M, N, K;                   // K a multiple of 16 (zero padded)
+    const float* __restrict__ bias;
+    const float* __restrict__ zin; // EPI_DGRAD: pre-activation of the layer
+    int ldzin;
+    float* __restrict__ out;       // FP32 output (z, y or dW)
+    int ldout;
+    __bf16* __restrict__ act;      // bf16 [M][N]
+    int ldact;
+    __bf16* __restrict__ actT;     // bf16 [N][M]
+    int ldactT;
+    int epi;
+};
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+
+__device__ __forceinline__ float gelu_grad(float z)
+{
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+}
+
+// One workgroup of 4 waves computes a 64 x 64 tile of C; each wave a 32 x 32
+// block with v_mfma_f32_32x32x16_bf16.  Lane l holds A[row l%32][k0 + 8(l/32)
+// .. +7] and B[col l%32][same k] and accumulates C element e at row
+// 8(e/4) + 4(l/32) + e%4, column l%32 of the wave's block.
+__global__ void __launch_bounds__(256) k_gemm_nt(GemmArgs g)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int m0 = blockIdx.y * 64 + (w >> 1) * 32;
+    const int n0 = blockIdx.x * 64 + (w & 1) * 32;
+    const int ra = m0 + (lane & 31), rb = n0 + (lane & 31);
+    const int kk = 8 * (lane >> 5);
+    const bool a_ok = ra < g.M, b_ok = rb < g.N;
+    const __bf16* pa = g.A + (size_t)(a_ok ? ra : 0) * g.lda + kk;
+    const __bf16* pb = g.B + (size_t)(b_ok ? rb : 0) * g.ldb + kk;
+    f32x16 acc = {0};
+    const bf16x8 zero = {0};
+#pragma unroll 8
+    for (int k0 = 0; k0 < g.K; k0 += 16) {
+        const bf16x8 a = a_ok ? *reinterpret_cast<const bf16x8*>(pa + k0) : zero;
+        const bf16x8 b = b_ok ? *reinterpret_cast<const bf16x8*>(pb + k0) : zero;
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+    const int col = n0 + (lane & 31);
+    if (col >= g.N) return;
+    const float bcol = (g.epi == EPI_HIDDEN || g.epi == EPI_OUTPUT) ? g.bias[col] : 0.0f;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int row = m0 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+        if (row >= g.M) continue;
+        const float v = acc[e];
+        switch (g.epi) {
+        case EPI_HIDDEN: {
+            const float z = v + bcol;
+            g.out[(size_t)row * g.ldout + col] = z;
+            const __bf16 h = (__bf16)gelu(z);
+            g.act[(size_t)row * g.ldact + col] = h;
+            g.actT[(size_t)col * g.ldactT + row] = h;
+            break;
+        }
+        case EPI_OUTPUT:
+            g.out[(size_t)row * g.ldout + col] = v + bcol;
+            break;
+        case EPI_DGRAD: {
+            const __bf16 d = (__bf16)(v * gelu_grad(g.zin[(size_t)row * g.ldzin + col]));
+            g.act[(size_t)row * g.ldact + col] = d;
+            g.actT[(size_t)col * g.ldactT + row] = d;
+            break;
+        }
+        default:
+            g.out[(size_t)row * g.ldout + col] = v;
+            break;
+        }
+    }
+}
+
+// Fixed-order workgroup sum (blockDim.x a power of two, <= 1024).
+__device__ double mlp_block_sum(double v, double* sh)
+{
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
+        if (t < s) sh[t] += sh[t + s];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+// Input: FP32 [M][d] -> bf16 [M][ld] and [ld][M]-transposed, zero padded.
+__global__ void k_mlp_input(const float* __restrict__ x, int M, int d, int pad, __bf16* __restrict__ a, int lda,
+                            __bf16* __restrict__ at, int ldat)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= M * pad) return;
+    const int m = idx / pad, k = idx % pad;
+    const __bf16 v = (__bf16)(k < d ? x[(size_t)m * d + k] : 0.0f);
+    a[(size_t)m * lda + k] = v;
+    at[(size_t)k * ldat + m] = v;
+}
+
+// MSE loss over the first dout columns and its gradient 2 (y - t) / (M dout)
+// as bf16 in both layouts (padded columns get 0).  One workgroup.
+__global__ void __launch_bounds__(1024) k_mlp_loss(const float* __restrict__ y, int ldy, const float* __restrict__ t,
+                                                   int M, int dout, int pad, __bf16* __restrict__ dz, int lddz,
+                                                   __bf16* __restrict__ dzt, int lddzt, float* __restrict__ loss)
+{
+    __shared__ double sh[1024];
+    const double scale = 1.0 / ((double)M * dout);
+    double acc = 0.0;
+    for (int idx = threadIdx.x; idx < M * pad; idx += blockDim.x) {
+        const int m = idx / pad, n = idx % pad;
+        float g = 0.0f;
+        if (n < dout) {
+            const float r = y[(size_t)m * ldy + n] - t[(size_t)m * dout + n];
+            acc += (double)r * r;
+            g = (float)(2.0 * scale) * r;
+        }
+        const __bf16 h = (__bf16)g;
+        dz[(size_t)m * lddz + n] = h;
+        dzt[(size_t)n * lddzt + m] = h;
+    }
+    acc = mlp_block_sum(acc, sh);
+    if (threadIdx.x == 0) *loss = (float)(acc * scale);
+}
+
+// Bias gradients db[n] = sum_m dz[m][n] from the transposed copy; one wave per n.
+__global__ void __launch_bounds__(256) k_mlp_bias_grad(const __bf16* __restrict__ dzt, int lddzt, int M, int N,
+                                                       float* __restrict__ db)
+{
+    const int n = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (n >= N) return;
+    float s = 0.0f;
+    for (int m = lane; m < M; m += 64) s += (float)dzt[(size_t)n * lddzt + m];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) db[n] = s;
+}
+
+// AdamW (decoupled weight decay) on FP32 master weights [N][ld] (and a bias
+// when wbf == nullptr); refreshes the bf16 copies [N][ld] and [ld][ldT].
+struct AdamArgs {
+    float* w;
+    const float* g;
+    float* m;
+    float* v;
+    __bf16* wbf;
+    __bf16* wtbf;
+    int rows, cols, ld, ldT, count;
+    float lr, b1, b2, eps, wd, c1, c2;   // c1 = 1 - b1^t, c2 = 1 - b2^t
+};
+
+__global__ void k_adamw(AdamArgs a)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.count) return;
+    const float g = a.g[idx];
+    const float m = a.b1 * a.m[idx] + (1.0f - a.b1) * g;
+    const float v = a.b2 * a.v[idx] + (1.0f - a.b2) * g * g;
+    a.m[idx] = m;
+    a.v[idx] = v;
+    const float mh = m / a.c1, vh = v / a.c2;
+    float w = a.w[idx];
+    w -= a.lr * (mh / (sqrtf(vh) + a.eps) + a.wd * w);
+    a.w[idx] = w;
+    if (a.wbf) {
+        const int r = idx / a.ld, c = idx % a.ld;
+        a.wbf[idx] = (__bf16)w;
+        a.wtbf[(size_t)c * a.ldT + r] = (__bf16)w;
+    }
+}
+
+// Refresh the bf16 copies of a weight matrix from its FP32 master.
+__global__ void k_weight_copies(const float* __restrict__ w, int count, int ld, int ldT, __bf16* __restrict__ wbf,
+                                __bf16* __restrict__ wtbf)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= count) return;
+    const int r = idx / ld, c = idx % ld;
+    wbf[idx] = (__bf16)w[idx];
+    wtbf[(size_t)c * ldT + r] = (__bf16)w[idx];
+}
+
+}  // namespace fk
+
+using namespace fk;
+
+struct fk_mlp {
+    int L = 0;
+    int dims[kMaxLayers + 1] = {0};
+    int pad[kMaxLayers + 1] = {0};      // dims[0] padded to 16, others to 32
+    int max_batch = 0;
+    int last_m = -1;                     // batch of the last forward
+    hipStream_t stream = nullptr;
+    void* pool = nullptr;
+    float *w[kMaxLayers], *b[kMaxLayers], *gw[kMaxLayers], *gb[kMaxLayers];
+    float *mw[kMaxLayers], *vw[kMaxLayers], *mb[kMaxLayers], *vb[kMaxLayers];
+    __bf16 *wbf[kMaxLayers], *wtbf[kMaxLayers];
+    __bf16 *act[kMaxLayers + 1], *actT[kMaxLayers + 1];
+    float* z[kMaxLayers + 1];
+    __bf16 *dz[kMaxLayers + 1], *dzT[kMaxLayers + 1];
+    float* loss = nullptr;
+    std::string err;
+};
+
+namespace {
+
+int mfail(fk_mlp* n, hipError_t e, const char* what)
+{
+    return set_error(n ? &n->err : nullptr, FK_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define FK_MHIP(n, call)                                    \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return mfail((n), e_, #call); \
+    } while (0)
+
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+void launch_gemm(const fk_mlp* n, const GemmArgs& g)
+{
+    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
+    hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, n->stream, g);
+}
+
+}  // namespace
+
+extern "C" int fk_mlp_create(int n_layers, const int32_t* dims, int max_batch, void* stream, fk_mlp** out)
+{
+    if (!out || !dims || n_layers < 1 || n_layers > kMaxLayers || max_batch < 16 || max_batch % 16)
+        return set_error(nullptr, FK_E_INVALID, "fk_mlp_create: 1..8 layers and max_batch a positive multiple of 16");
+    for (int l = 0; l <= n_layers; ++l)
+        if (dims[l] < 1 || dims[l] > 8192) return set_error(nullptr, FK_E_INVALID, "fk_mlp_create: widths in [1, 8192]");
+    fk_mlp* n = new (std::nothrow) fk_mlp();
+    if (!n) return set_error(nullptr, FK_E_OOM, "host allocation failed");
+    n->L = n_layers;
+    n->max_batch = max_batch;
+    n->stream = static_cast<hipStream_t>(stream);
+    for (int l = 0; l <= n_layers; ++l) {
+        n->dims[l] = dims[l];
+        n->pad[l] = l == 0 ? round_up(dims[l], 16) : round_up(dims[l], 32);
+    }
+    // one pool: parameters, gradients, moments, bf16 copies, activations
+    size_t off = 0;
+    std::vector<std::pair<void**, size_t>> want;
+    auto need = [&](void** p, size_t bytes) { want.push_back({p, bytes}); };
+    const size_t M = max_batch;
+    for (int l = 0; l < n_layers; ++l) {
+        const size_t wn = (size_t)n->pad[l + 1] * n->pad[l], bn = n->pad[l + 1];
+        need((void**)&n->w[l], wn * 4); need((void**)&n->gw[l], wn * 4);
+        need((void**)&n->mw[l], wn * 4); need((void**)&n->vw[l], wn * 4);
+        need((void**)&n->b[l], bn * 4); need((void**)&n->gb[l], bn * 4);
+        need((void**)&n->mb[l], bn * 4); need((void**)&n->vb[l], bn * 4);
+        need((void**)&n->wbf[l], wn * 2); need((void**)&n->wtbf[l], wn * 2);
+    }
+    for (int l = 0; l <= n_layers; ++l) {
+        need((void**)&n->act[l], M * n->pad[l] * 2); need((void**)&n->actT[l], M * n->pad[l] * 2);
+        need((void**)&n->z[l], M * n->pad[l] * 4);
+        need((void**)&n->dz[l], M * n->pad[l] * 2); need((void**)&n->dzT[l], M * n->pad[l] * 2);
+    }
+    need((void**)&n->loss, 256);
+    for (auto& q : want) off += (q.second + 255) & ~size_t(255);
+    if (hipMalloc(&n->pool, off) != hipSuccess) {
+        delete n;
+        return set_error(nullptr, FK_E_OOM, "device allocation of the network failed");
+    }
+    char* base = static_cast<char*>(n->pool);
+    off = 0;
+    for (auto& q : want) {
+        *q.first = base + off;
+        off += (q.second + 255) & ~size_t(255);
+    }
+    if (hipMemsetAsync(n->pool, 0, off, n->stream) != hipSuccess || hipStreamSynchronize(n->stream) != hipSuccess) {
+        (void)hipFree(n->pool);
+        delete n;
+        return set_error(nullptr, FK_E_HIP, "clearing the network memory failed");
+    }
+    *out = n;
+    return FK_OK;
+}
+
+extern "C" int fk_mlp_destroy(fk_mlp* n)
+{
+    if (!n) return FK_E_INVALID;
+    (void)hipStreamSynchronize(n->stream);
+    if (n->pool) (void)hipFree(n->pool);
+    delete n;
+    return FK_OK;
+}
+
+extern "C" const char* fk_mlp_last_error(const fk_mlp* n) { return n ? n->err.c_str() : global_error(); }
+
+extern "C" int fk_mlp_num_params(const fk_mlp* n, int64_t* count)
+{
+    if (!n || !count) return FK_E_INVALID;
+    int64_t c = 0;
+    for (int l = 0; l < n->L; ++l) c += (int64_t)n->dims[l + 1] * n->dims[l] + n->dims[l + 1];
+    *count = c;
+    return FK_OK;
+}
+
+namespace {
+
+// copy between the flat [W_1 (out x in), b_1, W_2, b_2, ...] vector and the
+// padded device arrays; which = 0: parameters, 1: gradients
+int flat_copy(fk_mlp* n, float* flat, int on_device, int which, bool to_net)
+{
+    const hipMemcpyKind kind = to_net ? (on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice)
+                                      : (on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost);
+    size_t off = 0;
+    for (int l = 0; l < n->L; ++l) {
+        const int in = n->dims[l], outd = n->dims[l + 1], ld = n->pad[l];
+        float* wd = which ? n->gw[l] : n->w[l];
+        float* bd = which ? n->gb[l] : n->b[l];
+        if (to_net)
+            FK_MHIP(n, hipMemcpy2DAsync(wd, ld * 4, flat + off, in * 4, in * 4, outd, kind, n->stream));
+        else
+            FK_MHIP(n, hipMemcpy2DAsync(flat + off, in * 4, wd, ld * 4, in * 4, outd, kind, n->stream));
+        off += (size_t)in * outd;
+        if (to_net) FK_MHIP(n, hipMemcpyAsync(bd, flat + off, outd * 4, kind, n->stream));
+        else FK_MHIP(n, hipMemcpyAsync(flat + off, bd, outd * 4, kind, n->stream));
+        off += outd;
+        if (to_net && which == 0) {
+            const int count = n->pad[l + 1] * ld;
+            hipLaunchKernelGGL(k_weight_copies, dim3((count + 255) / 256), dim3(256), 0, n->stream, n->w[l], count,
+                               ld, n->pad[l + 1], n->wbf[l], n->wtbf[l]);
+        }
+    }
+    FK_MHIP(n, hipStreamSynchronize(n->stream));
+    return FK_OK;
+}
+
+}  // namespace
+
+extern "C" int fk_mlp_set_params(fk_mlp* n, const float* src, int src_on_device)
+{
+    if (!n || !src) return FK_E_INVALID;
+    return flat_copy(n, const_cast<float*>(src), src_on_device, 0, true);
+}
+
+extern "C" int fk_mlp_get_params(fk_mlp* n, float* dst, int dst_on_device)
+{
+    if (!n || !dst) return FK_E_INVALID;
+    return flat_copy(n, dst, dst_on_device, 0, false);
+}
+
+extern "C" int fk_mlp_get_grads(fk_mlp* n, float* dst, int dst_on_device)
+{
+    if (!n || !dst) return FK_E_INVALID;
+    return flat_copy(n, dst, dst_on_device, 1, false);
+}
+
+extern "C" int fk_mlp_forward(fk_mlp* n, const float* x, int M, float* y)
+{
+    if (!n || !x || M < 1 || M > n->max_batch) return set_error(n ? &n->err : nullptr, FK_E_INVALID, "bad fk_mlp_forward arguments");
+    const int mb = n->max_batch;
+    {
+        const int count = M * n->pad[0];
+        hipLaunchKernelGGL(k_mlp_input, dim3((count + 255) / 256), dim3(256), 0, n->stream, x, M, n->dims[0],
+                           n->pad[0], n->act[0], n->pad[0], n->actT[0], mb);
+    }
+    for (int l = 0; l < n->L; ++l) {
+        GemmArgs g{};
+        g.A = n->act[l];
+        g.lda = n->pad[l];
+        g.B = n->wbf[l];
+        g.ldb = n->pad[l];
+        g.M = M;
+        g.N = n->pad[l + 1];
+        g.K = n->pad[l];
+        g.bias = n->b[l];
+        g.out = n->z[l + 1];
+        g.ldout = n->pad[l + 1];
+        g.act = n->act[l + 1];
+        g.ldact = n->pad[l + 1];
+        g.actT = n->actT[l + 1];
+        g.ldactT = mb;
+        g.epi = l + 1 < n->L ? EPI_HIDDEN : EPI_OUTPUT;
+        launch_gemm(n, g);
+    }
+    if (y)
+        FK_MHIP(n, hipMemcpy2DAsync(y, n->dims[n->L] * 4, n->z[n->L], n->pad[n->L] * 4, n->dims[n->L] * 4, M,
+                                    hipMemcpyDeviceToDevice, n->stream));
+    FK_MHIP(n, hipGetLastError());
+    n->last_m = M;
+    return FK_OK;
+}
+
+extern "C" int fk_mlp_backward(fk_mlp* n, const float* target, int M, float* loss_host)
+{
+    if (!n || !target || M != n->last_m || M % 16)
+        return set_error(n ? &n->err : nullptr, FK_E_INVALID, "fk_mlp_backward needs the batch of the last forward (a multiple of 16)");
+    const int mb = n->max_batch, L = n->L;
+    hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(1024), 0, n->stream, n->z[L], n->pad[L], target, M, n->dims[L],
+                       n->pad[L], n->dz[L], n->pad[L], n->dzT[L], mb, n->loss);
+    for (int l = L; l >= 1; --l) {
+        // weight and bias gradients of layer l (1-based): dW = dZ_l^T A_{l-1}
+        GemmArgs g{};
+        g.A = n->dzT[l];
+        g.lda = mb;
+        g.B = n->actT[l - 1];
+        g.ldb = mb;
+        g.M = n->pad[l];
+        g.N = n->pad[l - 1];
+        g.K = M;
+        g.out = n->gw[l - 1];
+        g.ldout = n->pad[l - 1];
+        g.epi = EPI_WGRAD;
+        launch_gemm(n, g);
+        hipLaunchKernelGGL(k_mlp_bias_grad, dim3((n->pad[l] + 3) / 4), dim3(256), 0, n->stream, n->dzT[l], mb, M,
+                           n->pad[l], n->gb[l - 1]);
+        if (l > 1) {
+            // gradient of the pre-activation of layer l-1: dZ_{l-1} = (dZ_l W_l) * gelu'(Z_{l-1})
+            GemmArgs d{};
+            d.A = n->dz[l];
+            d.lda = n->pad[l];
+            d.B = n->wtbf[l - 1];
+            d.ldb = n->pad[l];
+            d.M = M;
+            d.N = n->pad[l - 1];
+            d.K = n->pad[l];
+            d.zin = n->z[l - 1];
+            d.ldzin = n->pad[l - 1];
+            d.act = n->dz[l - 1];
+            d.ldact = n->pad[l - 1];
+            d.actT = n->dzT[l - 1];
+            d.ldactT = mb;
+            d.epi = EPI_DGRAD;
+            launch_gemm(n, d);
+        }
+    }
+    FK_MHIP(n, hipGetLastError());
+    if (loss_host) {
+        FK_MHIP(n, hipMemcpyAsync(loss_host, n->loss, sizeof(float), hipMemcpyDeviceToHost, n->stream));
+        FK_MHIP(n, hipStreamSynchronize(n->stream));
+    }
+    return FK_OK;
+}
+
+extern "C" int fk_mlp_adamw(fk_mlp* n, double lr, double beta1, double beta2, double eps, double weight_decay,
+                            int64_t step)
+{
+    if (!n || step < 1) return FK_E_INVALID;
+    for (int l = 0; l < n->L; ++l) {
+        AdamArgs a{};
+        a.lr = (float)lr;
+        a.b1 = (float)beta1;
+        a.b2 = (float)beta2;
+        a.eps = (float)eps;
+        a.c1 = (float)(1.0 - std::pow(beta1, (double)step));
+        a.c2 = (float)(1.0 - std::pow(beta2, (double)step));
+        a.w = n->w[l];
+        a.g = n->gw[l];
+        a.m = n->mw[l];
+        a.v = n->vw[l];
+        a.wbf = n->wbf[l];
+        a.wtbf = n->wtbf[l];
+        a.ld = n->pad[l];
+        a.ldT = n->pad[l + 1];
+        a.count = n->pad[l + 1] * n->pad[l];
+        a.wd = (float)weight_decay;
+        hipLaunchKernelGGL(k_adamw, dim3((a.count + 255) / 256), dim3(256), 0, n->stream, a);
+        AdamArgs c = a;   // biases: no weight decay, no bf16 copies
+        c.w = n->b[l];
+        c.g = n->gb[l];
+        c.m = n->mb[l];
+        c.v = n->vb[l];
+        c.wbf = nullptr;
+        c.wtbf = nullptr;
+        c.count = n->pad[l + 1];
+        c.ld = 1;
+        c.wd = 0.0f;
+        hipLaunchKernelGGL(k_adamw, dim3((c.count + 255) / 256), dim3(256), 0, n->stream, c);
+    }
+    FK_MHIP(n, hipGetLastError());
+    return FK_OK;
+}
+
+extern "C" int fk_mlp_sync(fk_mlp* n)
+{
+    if (!n) return FK_E_INVALID;
+    FK_MHIP(n, hipStreamSynchronize(n->stream));
+    return FK_OK;
+}

@@ -105,6 +105,17 @@ SIGNATURES = {
     "fk_batch_get": (C.c_int, [_vp, C.c_int, _P(_ctx)]),
     "fk_batch_info": (C.c_int, [_vp, _P(fk_batch_info_t)]),
     "fk_batch_last_error": (C.c_char_p, [_vp]),
+    "fk_mlp_create": (C.c_int, [C.c_int, _P(C.c_int32), C.c_int, _vp, _P(_vp)]),
+    "fk_mlp_destroy": (C.c_int, [_vp]),
+    "fk_mlp_last_error": (C.c_char_p, [_vp]),
+    "fk_mlp_num_params": (C.c_int, [_vp, _P(C.c_int64)]),
+    "fk_mlp_set_params": (C.c_int, [_vp, _vp, C.c_int]),
+    "fk_mlp_get_params": (C.c_int, [_vp, _vp, C.c_int]),
+    "fk_mlp_get_grads": (C.c_int, [_vp, _vp, C.c_int]),
+    "fk_mlp_forward": (C.c_int, [_vp, _vp, C.c_int, _vp]),
+    "fk_mlp_backward": (C.c_int, [_vp, _vp, C.c_int, _P(C.c_float)]),
+    "fk_mlp_adamw": (C.c_int, [_vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int64]),
+    "fk_mlp_sync": (C.c_int, [_vp]),
 }
 for _name, (_res, _args) in SIGNATURES.items():
     _fn = getattr(_lib, _name)
@@ -340,3 +351,64 @@ class Batch:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class MLP:
+    """The surrogate network on the GPU (fk_mlp_*).  Inputs, outputs and
+    targets are device pointers (e.g. torch tensor data_ptr())."""
+
+    def __init__(self, dims, max_batch=256, stream=None):
+        self.dims = list(dims)
+        arr = (C.c_int32 * len(self.dims))(*self.dims)
+        h = _vp()
+        rc = fk_mlp_create(len(self.dims) - 1, arr, int(max_batch), stream, C.byref(h))
+        if rc != OK:
+            raise FlashkinError(rc, (fk_mlp_last_error(None) or b"").decode())
+        self._h = h
+        n = C.c_int64()
+        self._chk(fk_mlp_num_params(self._h, C.byref(n)))
+        self.n_params = n.value
+
+    def _chk(self, rc):
+        if rc != OK:
+            raise FlashkinError(rc, (fk_mlp_last_error(self._h) or b"").decode())
+
+    def set_params(self, flat):
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        assert a.size == self.n_params
+        self._chk(fk_mlp_set_params(self._h, a.ctypes.data, 0))
+
+    def params(self):
+        out = np.empty(self.n_params, dtype=np.float32)
+        self._chk(fk_mlp_get_params(self._h, out.ctypes.data, 0))
+        return out
+
+    def grads(self):
+        out = np.empty(self.n_params, dtype=np.float32)
+        self._chk(fk_mlp_get_grads(self._h, out.ctypes.data, 0))
+        return out
+
+    def forward(self, x_ptr, m, y_ptr=None):
+        self._chk(fk_mlp_forward(self._h, x_ptr, int(m), y_ptr))
+
+    def backward(self, t_ptr, m):
+        loss = C.c_float()
+        self._chk(fk_mlp_backward(self._h, t_ptr, int(m), C.byref(loss)))
+        return loss.value
+
+    def adamw(self, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=1e-4):
+        self._chk(fk_mlp_adamw(self._h, lr, beta1, beta2, eps, weight_decay, int(step)))
+
+    def sync(self):
+        self._chk(fk_mlp_sync(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            fk_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
