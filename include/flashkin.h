@@ -190,6 +190,21 @@ int fk_read_trace(fk_ctx* ctx, fk_state* dst, size_t cap, size_t* n_out);
 int fk_write_state(fk_ctx* ctx, const void* f, int src_on_device, double sigma, double sigma_lo,
                    int64_t step);
 
+/* The x-resolved enclosed charge sigma_enc(x) = 2 eps0 E_x(x) (equal to
+ * sigma at the dielectric) of the current state at npts >= 2 uniform points
+ * x_p = p L / (npts - 1), piecewise linear between the cell centres; into
+ * out (host, or device if dst_on_device). */
+int fk_read_profile(fk_ctx* ctx, int npts, double* out, int dst_on_device);
+
+/* Warm start from a predicted profile (npts >= 2 values of sigma_enc at the
+ * uniform points above; host or device memory): sigma = profile[0] and
+ * f(x_k, v) = n_k M(v), where n_k = (S(k dx) - S((k+1) dx)) / (2 e dx) is the
+ * cell-averaged electron density whose enclosed charge is the piecewise-
+ * linear profile S (clamped at zero) and M the Maxwellian at t_ev normalised
+ * on the velocity grid.  The step counter is set to step; otherwise as
+ * fk_write_state. */
+int fk_warm_start(fk_ctx* ctx, const double* profile, int npts, int src_on_device, double t_ev, int64_t step);
+
 /* Saturation test of Section 2 (sigma, Gamma_pe and Gamma_see each change
  * by at most rtol relative within a window of window_s seconds), applied to
  * the trace history drained so far (the call drains the ring first).
@@ -244,8 +259,10 @@ int fk_batch_destroy(fk_batch* batch);
 /* Queue nsteps steps of every instance (asynchronous). */
 int fk_batch_step(fk_batch* batch, int64_t nsteps);
 
-/* Wait; returns the first instance error (CFL, non-finite) and its index in
- * *first_bad (-1 if none; may be NULL). */
+/* Wait; returns the first error (CFL, non-finite) among the active
+ * instances and its index in *first_bad (-1 if none; may be NULL).  After an
+ * error fk_batch_step refuses to run until the flagged instances are retired;
+ * the others are unaffected (instances share no data). */
 int fk_batch_sync(fk_batch* batch, int* first_bad);
 
 /* Non-owning view of instance i, valid until fk_batch_destroy: the fk_read_*,
@@ -254,6 +271,11 @@ int fk_batch_sync(fk_batch* batch, int* first_bad);
 int fk_batch_get(fk_batch* batch, int i, fk_ctx** view);
 
 int fk_batch_info(const fk_batch* batch, fk_batch_info_t* out);
+
+/* Stop stepping instances idx[0..n-1] (e.g. saturated or flagged ones);
+ * their state stays readable through the views.  Clears the batch's pending
+ * error and rebuilds the work list and graphs. */
+int fk_batch_retire(fk_batch* batch, const int* idx, int n);
 const char* fk_batch_last_error(const fk_batch* batch);
 
 /* ---- surrogate network ---------------------------------------------------

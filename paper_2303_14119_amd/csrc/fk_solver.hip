@@ -151,6 +151,78 @@ __global__ void __launch_bounds__(kFieldThreads) k_field(FieldArgs a)
     field_block(a, sh);
 }
 
+// ---------------------------------------------------------------- profile
+
+// Value of the x-resolved enclosed charge sigma_enc(x) = 2 eps0 E_x(x),
+// piecewise linear through (0, sigma), the cell centres (x_k, 2 eps0 E_x,k)
+// and flat beyond the last centre.
+__device__ double enclosed_at(const double* ex, double sigma, int nx, double dx, double x)
+{
+    if (x <= 0.5 * dx) {
+        const double s1 = 2.0 * kEps0 * ex[0];
+        return sigma + (s1 - sigma) * (x / (0.5 * dx));
+    }
+    const double u = x / dx - 0.5;
+    int k = (int)floor(u);
+    if (k >= nx - 1) return 2.0 * kEps0 * ex[nx - 1];
+    const double w = u - k;
+    return 2.0 * kEps0 * ((1.0 - w) * ex[k] + w * ex[k + 1]);
+}
+
+__global__ void k_profile(const double* __restrict__ ex, const DevState* __restrict__ st, int nx, double dx,
+                          double length, int npts, double* __restrict__ out)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npts) return;
+    const double x = length * p / (npts - 1);
+    out[p] = enclosed_at(ex, st->sigma + st->sigma_lo, nx, dx, x);
+}
+
+// Piecewise-linear interpolation of a profile given at npts uniform points.
+__device__ double profile_at(const double* prof, int npts, double length, double x)
+{
+    const double u = fmin(fmax(x / length, 0.0), 1.0) * (npts - 1);
+    int q = (int)floor(u);
+    if (q >= npts - 1) q = npts - 2;
+    const double w = u - q;
+    return (1.0 - w) * prof[q] + w * prof[q + 1];
+}
+
+// Normalisation of the emission-temperature Maxwellian on the velocity grid:
+// out = 1 / sum exp(-m v^2 / 2T) dv_x dv_y (one workgroup).
+__global__ void __launch_bounds__(kFieldThreads) k_warm_norm(int nvx, int nvy, double dvx, double dvy, double t_ev,
+                                                             double* out)
+{
+    __shared__ double sh[kFieldThreads];
+    double s = 0.0;
+    for (int m = threadIdx.x; m < nvx * nvy; m += blockDim.x) {
+        const double vx = cell_v(m / nvy, nvx, dvx), vy = cell_v(m % nvy, nvy, dvy);
+        s += exp(-kMe * (vx * vx + vy * vy) / (2.0 * t_ev * kE)) * dvx * dvy;
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) *out = s > 0.0 ? 1.0 / s : 0.0;
+}
+
+// Warm start: f(x_k, v) = n_k M(v) with n_k = (S(k dx) - S((k+1) dx)) / (2 e dx)
+// (clamped at 0): the electron density whose enclosed charge is the profile
+// S, averaged over cell k, times the normalised Maxwellian at t_ev.
+template <typename T>
+__global__ void k_warm_start(T* __restrict__ f, const double* __restrict__ prof, int npts, double length, int nx,
+                             int nvx, int nvy, double dx, double dvx, double dvy, double t_ev,
+                             const double* __restrict__ norm)
+{
+    const size_t cells = (size_t)nx * nvx * nvy;
+    const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+    const int k = (int)(c / ((size_t)nvx * nvy));
+    const int m = (int)(c % ((size_t)nvx * nvy));
+    const double s0 = profile_at(prof, npts, length, k * dx);
+    const double s1 = profile_at(prof, npts, length, (k + 1) * dx);
+    const double nk = fmax(0.0, (s0 - s1) / (2.0 * kE * dx));
+    const double vx = cell_v(m / nvy, nvx, dvx), vy = cell_v(m % nvy, nvy, dvy);
+    f[c] = T(nk * *norm * exp(-kMe * (vx * vx + vy * vy) / (2.0 * t_ev * kE)));
+}
+
 }  // namespace fk
 
 using namespace fk;
@@ -523,10 +595,16 @@ int drain(fk_ctx* c, size_t* fresh_begin)
     }
     const int64_t n = last_rec - first_rec + 1;
     if (n > 0) {
-        std::vector<fk_state> tmp((size_t)cap);
-        FK_HIP(c, hipMemcpyAsync(tmp.data(), c->b.ring, sizeof(fk_state) * cap, hipMemcpyDeviceToHost, c->stream));
+        // copy only the slots of the new records (one or two ranges of the ring)
+        std::vector<fk_state> tmp((size_t)n);
+        const int64_t s0 = first_rec % cap;
+        const int64_t n1 = std::min(n, cap - s0);
+        FK_HIP(c, hipMemcpyAsync(tmp.data(), c->b.ring + s0, sizeof(fk_state) * n1, hipMemcpyDeviceToHost, c->stream));
+        if (n1 < n)
+            FK_HIP(c, hipMemcpyAsync(tmp.data() + n1, c->b.ring, sizeof(fk_state) * (n - n1), hipMemcpyDeviceToHost,
+                                     c->stream));
         FK_HIP(c, hipStreamSynchronize(c->stream));
-        for (int64_t r = first_rec; r <= last_rec; ++r) c->history.push_back(tmp[(size_t)(r % cap)]);
+        c->history.insert(c->history.end(), tmp.begin(), tmp.end());
         c->drained_step = last_rec * stride;
     }
     if (code) set_error(&c->err, code, "trace ring overflowed; older records were lost");
@@ -999,6 +1077,9 @@ struct fk_batch {
     hipStream_t cap_stream = nullptr;
     int ti = 8;
     int sched = 0;                // 0 dynamic (atomic counter), 1 static round-robin
+    int occ = 0;                  // workgroups per compute unit (0 = occupancy limit)
+    std::vector<char> active;     // instances still stepped
+    int n_active = 0;
     int grid = 0;
     size_t lds = 0;
     int max_blocks_x = 1;
@@ -1043,8 +1124,8 @@ void batch_launch_step(const fk_batch* b, int from, hipStream_t s)
     else
         hipLaunchKernelGGL(k_batch_sweep<8>, dim3(b->grid), dim3(kBatchThreads), b->lds, s, b->d_inst, b->d_items,
                            (int)n_items, b->d_counter, from, b->sched);
-    hipLaunchKernelGGL(k_batch_reduce, dim3(b->max_blocks_x, b->inst.size()), dim3(256), 0, s, b->d_inst);
-    hipLaunchKernelGGL(k_batch_field, dim3(b->inst.size()), dim3(kFieldThreads), 0, s, b->d_inst, b->d_counter, 1);
+    hipLaunchKernelGGL(k_batch_reduce, dim3(b->max_blocks_x, b->n_active), dim3(256), 0, s, b->d_inst);
+    hipLaunchKernelGGL(k_batch_field, dim3(b->n_active), dim3(kFieldThreads), 0, s, b->d_inst, b->d_counter, 1);
 }
 
 // (Re)build the instance descriptors and the work list for the members'
@@ -1056,8 +1137,16 @@ int batch_build(fk_batch* b, int wgs_per_cu)
     b->items_host.clear();
     b->lds = 0;
     b->max_blocks_x = 1;
-    for (size_t m = 0; m < b->inst.size(); ++m) {
-        fk_ctx* c = b->inst[m];
+    b->occ = wgs_per_cu;
+    if (b->active.size() != b->inst.size()) b->active.assign(b->inst.size(), 1);
+    std::vector<int> compact;
+    for (size_t m = 0; m < b->inst.size(); ++m)
+        if (b->active[m]) compact.push_back((int)m);
+    b->n_active = (int)compact.size();
+    if (b->n_active == 0) return FK_OK;
+    for (size_t q = 0; q < compact.size(); ++q) {
+        const size_t m = q;
+        fk_ctx* c = b->inst[compact[q]];
         BatchInst d{};
         d.sw[0] = sweep_args<float>(c, 0);
         d.sw[1] = sweep_args<float>(c, 1);
@@ -1086,7 +1175,7 @@ int batch_build(fk_batch* b, int wgs_per_cu)
     // largest items first
     std::stable_sort(b->items_host.begin(), b->items_host.end(), [&](const BatchItem& x, const BatchItem& y) {
         auto cost = [&](const BatchItem& t) {
-            const fk_ctx* c = b->inst[t.inst];
+            const fk_ctx* c = b->inst[compact[t.inst]];
             const int np = std::min(c->L.kc, c->p.nx - t.kci * c->L.kc);
             return (double)t.ntiles * np * c->p.nvy;
         };
@@ -1146,6 +1235,7 @@ void batch_release(fk_batch* b)
 
 int batch_steps(fk_batch* b, int64_t n)
 {
+    if (b->n_active == 0) return FK_OK;
     int64_t left = n;
     while (left >= b->graph_steps) {
         FK_BHIP(b, hipGraphLaunch(b->graph[b->cur], b->stream));
@@ -1156,7 +1246,8 @@ int batch_steps(fk_batch* b, int64_t n)
         b->cur ^= 1;
     }
     FK_BHIP(b, hipGetLastError());
-    for (auto c : b->inst) c->cur = b->cur;
+    for (size_t m = 0; m < b->inst.size(); ++m)
+        if (b->active[m]) b->inst[m]->cur = b->cur;
     return FK_OK;
 }
 
@@ -1291,6 +1382,7 @@ extern "C" int fk_batch_sync(fk_batch* b, int* first_bad)
     FK_BHIP(b, hipStreamSynchronize(b->stream));
     if (first_bad) *first_bad = -1;
     for (size_t m = 0; m < b->inst.size(); ++m) {
+        if (!b->active[m]) continue;
         int rc = fk_sync(b->inst[m]);
         if (rc) {
             b->sticky = rc;
@@ -1325,3 +1417,72 @@ extern "C" int fk_batch_info(const fk_batch* b, fk_batch_info_t* out)
 }
 
 extern "C" const char* fk_batch_last_error(const fk_batch* b) { return b ? b->err.c_str() : global_error(); }
+
+
+extern "C" int fk_read_profile(fk_ctx* c, int npts, double* out, int dst_on_device)
+{
+    if (!c || !out || npts < 2) return FK_E_INVALID;
+    double* d = out;
+    double* tmp = nullptr;
+    if (!dst_on_device) {
+        FK_HIP(c, hipMalloc(&tmp, (size_t)npts * sizeof(double)));
+        d = tmp;
+    }
+    hipLaunchKernelGGL(k_profile, dim3((npts + 255) / 256), dim3(256), 0, c->stream, c->b.ex, c->b.st, c->p.nx,
+                       c->L.dx, c->p.length_m, npts, d);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && tmp) e = hipMemcpyAsync(out, tmp, (size_t)npts * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (tmp) (void)hipFree(tmp);
+    if (e != hipSuccess) return hip_fail(c, e, "fk_read_profile");
+    return FK_OK;
+}
+
+extern "C" int fk_warm_start(fk_ctx* c, const double* profile, int npts, int src_on_device, double t_ev,
+                             int64_t step)
+{
+    if (!c || !profile || npts < 2 || !(t_ev > 0) || step < 0) return FK_E_INVALID;
+    FK_HIP(c, hipStreamSynchronize(c->stream));
+    std::vector<double> host(npts);
+    if (src_on_device)
+        FK_HIP(c, hipMemcpy(host.data(), profile, npts * sizeof(double), hipMemcpyDeviceToHost));
+    else
+        std::memcpy(host.data(), profile, npts * sizeof(double));
+    for (double v : host)
+        if (!std::isfinite(v)) return set_error(&c->err, FK_E_INVALID, "profile has non-finite values");
+    double* dprof = nullptr;
+    FK_HIP(c, hipMalloc(&dprof, npts * sizeof(double)));
+    hipError_t e = hipMemcpyAsync(dprof, host.data(), npts * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_warm_norm, dim3(1), dim3(kFieldThreads), 0, c->stream, c->p.nvx, c->p.nvy, c->L.dvx,
+                           c->L.dvy, t_ev, c->b.consts + 4);
+        const size_t cells = (size_t)c->L.cells;
+        const dim3 grid((unsigned)((cells + 255) / 256));
+        if (c->L.elem == 4)
+            hipLaunchKernelGGL(k_warm_start<float>, grid, dim3(256), 0, c->stream, static_cast<float*>(c->b.f[c->cur]),
+                               dprof, npts, c->p.length_m, c->p.nx, c->p.nvx, c->p.nvy, c->L.dx, c->L.dvx, c->L.dvy,
+                               t_ev, c->b.consts + 4);
+        else
+            hipLaunchKernelGGL(k_warm_start<double>, grid, dim3(256), 0, c->stream, static_cast<double*>(c->b.f[c->cur]),
+                               dprof, npts, c->p.length_m, c->p.nx, c->p.nvx, c->p.nvy, c->L.dx, c->L.dvx, c->L.dvy,
+                               t_ev, c->b.consts + 4);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(dprof);
+    if (e != hipSuccess) return hip_fail(c, e, "fk_warm_start");
+    return fk_write_state(c, nullptr, 0, host[0], 0.0, step);
+}
+
+extern "C" int fk_batch_retire(fk_batch* b, const int* idx, int n)
+{
+    if (!b || (n && !idx)) return FK_E_INVALID;
+    for (int q = 0; q < n; ++q) {
+        if (idx[q] < 0 || idx[q] >= (int)b->inst.size()) return set_error(&b->err, FK_E_INVALID, "bad instance index");
+        b->active[idx[q]] = 0;
+    }
+    // instances are independent: once the flagged ones are retired the rest
+    // may go on (the next fk_batch_sync checks the active ones again)
+    b->sticky = FK_OK;
+    return batch_build(b, b->occ);
+}

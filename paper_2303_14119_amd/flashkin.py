@@ -105,6 +105,9 @@ SIGNATURES = {
     "fk_batch_get": (C.c_int, [_vp, C.c_int, _P(_ctx)]),
     "fk_batch_info": (C.c_int, [_vp, _P(fk_batch_info_t)]),
     "fk_batch_last_error": (C.c_char_p, [_vp]),
+    "fk_read_profile": (C.c_int, [_ctx, C.c_int, _vp, C.c_int]),
+    "fk_warm_start": (C.c_int, [_ctx, _vp, C.c_int, C.c_int, C.c_double, C.c_int64]),
+    "fk_batch_retire": (C.c_int, [_vp, _P(C.c_int), C.c_int]),
     "fk_mlp_create": (C.c_int, [C.c_int, _P(C.c_int32), C.c_int, _vp, _P(_vp)]),
     "fk_mlp_destroy": (C.c_int, [_vp]),
     "fk_mlp_last_error": (C.c_char_p, [_vp]),
@@ -263,6 +266,15 @@ class Solver:
         self._chk(fk_saturated(self._h, window_s, rtol, C.byref(out)))
         return bool(out.value)
 
+    def profile(self, npts=256):
+        out = np.empty(npts)
+        self._chk(fk_read_profile(self._h, int(npts), out.ctypes.data, 0))
+        return out
+
+    def warm_start(self, profile, t_ev, step=0):
+        a = np.ascontiguousarray(profile, dtype=np.float64)
+        self._chk(fk_warm_start(self._h, a.ctypes.data, a.size, 0, float(t_ev), int(step)))
+
     def set_profiling(self, on=True):
         self._chk(fk_set_profiling(self._h, 1 if on else 0))
 
@@ -300,9 +312,11 @@ class Batch:
     """Independent FP32 instances stepped together by one persistent launch
     per step (fk_batch_*)."""
 
-    def __init__(self, cfgs, stream=None, autotune=False, **kw):
+    def __init__(self, cfgs, stream=None, autotune=False, trace_stride=1, **kw):
         self.cfgs = list(cfgs)
-        arr = (fk_params * len(self.cfgs))(*[make_params(c, "f32", **kw) for c in self.cfgs])
+        strides = trace_stride if isinstance(trace_stride, (list, tuple)) else [trace_stride] * len(self.cfgs)
+        arr = (fk_params * len(self.cfgs))(*[make_params(c, "f32", trace_stride=st, **kw)
+                                             for c, st in zip(self.cfgs, strides)])
         h = _vp()
         rc = fk_batch_create(arr, len(self.cfgs), stream, 1 if autotune else 0, C.byref(h))
         if rc != OK:
@@ -323,10 +337,19 @@ class Batch:
         self._chk(fk_batch_step(self._h, int(n)))
 
     def sync(self):
+        """Wait; raises FlashkinError with ``.instance`` set to the first
+        flagged active instance."""
         bad = C.c_int(-1)
         rc = fk_batch_sync(self._h, C.byref(bad))
         if rc != OK:
-            raise FlashkinError(rc, (fk_batch_last_error(self._h) or b"").decode())
+            err = FlashkinError(rc, (fk_batch_last_error(self._h) or b"").decode())
+            err.instance = bad.value
+            raise err
+
+    def retire(self, idx):
+        idx = list(idx)
+        arr = (C.c_int * max(1, len(idx)))(*idx)
+        self._chk(fk_batch_retire(self._h, arr, len(idx)))
 
     def info(self):
         out = fk_batch_info_t()

@@ -1,0 +1,237 @@
+"""Surrogate of the saturated state and the warm start it feeds.
+
+A project addition beyond the paper: the paper advances every run from an
+empty domain to saturation (Section 3).  Here a multilayer perceptron maps a
+run's parameters (|E_y|, delta_max, A_max, T_se, L) to its saturated
+x-resolved enclosed charge sigma_enc(x) on 256 points plus the primary and
+secondary fluxes; its prediction initialises a new run, which then continues
+to saturation.  The plain cold start stays the fallback and the judge of the
+prediction's error.
+
+Every step runs in the library's kernels: the batched solver generates the
+data, fk_read_profile resamples it, the network trains with fk_mlp_* and
+fk_warm_start builds the initial state.  This module only moves arrays
+between them (torch holds the device buffers).
+"""
+import math
+import time
+
+import numpy as np
+
+from . import flashkin as fk
+from . import workloads as W
+
+NPTS = 256
+DIMS = [5, 512, 512, 512, 512, NPTS + 2]
+EPS0 = 8.8541878128e-12
+FEATURE_RANGES = np.array([(1e6, 10e6), (1.5, 3.5), (250.0, 600.0), (1.0, 5.0), (0.5e-3, 5e-3)])
+
+
+def features(cfgs):
+    """Inputs scaled to [-1, 1] from the sweep's ranges."""
+    raw = np.array([[abs(c["ey"]), c["delta_max"], c["a_max_ev"], c["t_se_ev"], c["length"]] for c in cfgs])
+    lo, hi = FEATURE_RANGES[:, 0], FEATURE_RANGES[:, 1]
+    return (2.0 * (raw - lo) / (hi - lo) - 1.0).astype(np.float32)
+
+
+def encode(profile, g_pe, g_see, ey):
+    """Targets: the profile in units of 2 eps0 |E_y| (the scale of Eq 20) and
+    the log10 fluxes, centred."""
+    scale = 2.0 * EPS0 * abs(ey)
+    lg = [(math.log10(max(g, 1e10)) - 24.0) / 2.0 for g in (g_pe, g_see)]
+    return np.concatenate([np.asarray(profile) / scale, lg]).astype(np.float32)
+
+
+def decode(y, ey):
+    scale = 2.0 * EPS0 * abs(ey)
+    y = np.asarray(y, dtype=np.float64)
+    return y[:NPTS] * scale, 10.0 ** (2.0 * y[NPTS] + 24.0), 10.0 ** (2.0 * y[NPTS + 1] + 24.0)
+
+
+def trace_stride(dt, every_s=1e-12):
+    return max(1, int(round(every_s / dt)))
+
+
+def run_to_saturation(batch, cfgs, window_s=50e-12, rtol=1e-3, t_max=3e-9, check_steps=400, log=None):
+    """Step a Batch, retiring instances once the Section 2 test holds or
+    their time exceeds t_max, and any instance the library flags (CFL or
+    non-finite; the rest go on).  Returns per instance (saturated, steps, t,
+    status) with status "ok" or the flag's message."""
+    n = len(cfgs)
+    done = [None] * n
+    dts = [v.dt for v in batch.views]
+    steps = 0
+    while any(d is None for d in done):
+        batch.step(check_steps)
+        steps += check_steps
+        while True:
+            try:
+                batch.sync()
+                break
+            except fk.FlashkinError as e:
+                m = getattr(e, "instance", -1)
+                if m < 0 or done[m] is not None:
+                    raise
+                done[m] = (False, steps, steps * dts[m], str(e))
+                batch.retire([m])
+                if log:
+                    log(f"  step {steps}: instance {m} flagged and retired: {e}")
+        retire = []
+        for m, v in enumerate(batch.views):
+            if done[m] is not None:
+                continue
+            t = steps * dts[m]
+            if v.saturated(window_s, rtol):
+                done[m] = (True, steps, t, "ok")
+                retire.append(m)
+            elif t >= t_max:
+                done[m] = (False, steps, t, "ok")
+                retire.append(m)
+        if retire:
+            batch.retire(retire)
+            if log:
+                log(f"  step {steps}: retired {len(retire)} (active {sum(d is None for d in done)})")
+    return done
+
+
+def generate(n_runs, seed, per_batch=64, t_max=3e-9, stream=None, log=None, retries=2):
+    """n_runs runs drawn like the batched sweep (seeded), each advanced to
+    saturation or t_max.  The step follows the CFL conditions of Section 2,
+    but it is fixed before the surface charge exists: a run whose self field
+    later drives the v_x Courant number above one is flagged by the library
+    and run again from the start at half the step (at most ``retries``
+    times).  Returns (cfgs, X features, Y targets, saturated flags, wall
+    seconds, failed) where failed lists (cfg, message) of runs still flagged
+    after the retries; those are left out of X and Y."""
+    rng = np.random.default_rng(seed)
+    todo = []
+    for b0 in range(0, n_runs, per_batch):
+        todo += W.c2_instances(seed=int(rng.integers(1 << 31)), n=min(per_batch, n_runs - b0))
+    cfgs_all, xs, ys, sat, failed = [], [], [], [], []
+    t0 = time.perf_counter()
+    attempt = 0
+    while todo:
+        again = []
+        for b0 in range(0, len(todo), per_batch):
+            cfgs = todo[b0:b0 + per_batch]
+            # record about every picosecond of each instance's own time
+            dts = [fk.validate(fk.make_params(c))["dt"] for c in cfgs]
+            strides = [trace_stride(dt) for dt in dts]
+            batch = fk.Batch(cfgs, stream=stream, autotune=False, trace_cap=8192, trace_stride=strides)
+            try:
+                done = run_to_saturation(batch, cfgs, t_max=t_max, log=log)
+                for c, dt, v, d in zip(cfgs, dts, batch.views, done):
+                    if d[3] != "ok":
+                        if attempt < retries:
+                            again.append(dict(c, dt=0.5 * dt))
+                        else:
+                            failed.append((c, d[3]))
+                        continue
+                    st = v.state()
+                    prof = v.profile(NPTS)
+                    cfgs_all.append(c)
+                    xs.append(features([c])[0])
+                    ys.append(encode(prof, st["g_pe"], st["g_see"], c["ey"]))
+                    sat.append(d[0])
+            finally:
+                batch.close()
+            if log:
+                log(f"pass {attempt} batch {b0 // per_batch}: {sum(sat)} / {len(sat)} saturated, "
+                    f"{len(again)} to rerun, {time.perf_counter() - t0:.1f} s")
+        todo = again
+        attempt += 1
+    return cfgs_all, np.array(xs), np.array(ys), np.array(sat), time.perf_counter() - t0, failed
+
+
+def init_params(dims, seed):
+    """Normal weights scaled by 1/sqrt(fan_in), zero biases, flat layout."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for l in range(len(dims) - 1):
+        parts.append((rng.standard_normal((dims[l + 1], dims[l])) / math.sqrt(dims[l])).ravel())
+        parts.append(np.zeros(dims[l + 1]))
+    return np.concatenate(parts).astype(np.float32)
+
+
+class Surrogate:
+    """The network on the GPU plus its training loop."""
+
+    def __init__(self, seed=0, batch=256, stream=None):
+        import torch
+        self.torch = torch
+        self.batch = batch
+        self.net = fk.MLP(DIMS, max_batch=batch, stream=stream)
+        self.net.set_params(init_params(DIMS, seed))
+        self.step = 0
+
+    def fit(self, X, Y, epochs=200, lr=1e-3, weight_decay=1e-4, seed=0, Xval=None, Yval=None, log=None):
+        torch = self.torch
+        rng = np.random.default_rng(seed)
+        n = len(X)
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        Y = np.ascontiguousarray(Y, dtype=np.float32)
+        hist = []
+        m = self.batch
+        for ep in range(epochs):
+            order = rng.permutation(n)         # shuffled on the host, uploaded per epoch
+            xs = torch.from_numpy(X[order]).cuda()
+            ys = torch.from_numpy(Y[order]).cuda()
+            losses = []
+            for lo in range(0, n - m + 1, m):
+                self.step += 1
+                # cosine decay of the learning rate over the run
+                frac = ep / max(1, epochs - 1)
+                lr_t = lr * (0.05 + 0.95 * 0.5 * (1 + math.cos(math.pi * frac)))
+                self.net.forward(xs[lo:lo + m].data_ptr(), m)
+                losses.append(self.net.backward(ys[lo:lo + m].data_ptr(), m))
+                self.net.adamw(self.step, lr=lr_t, weight_decay=weight_decay)
+            rec = {"epoch": ep, "train": float(np.mean(losses))}
+            if Xval is not None and (ep % 20 == 19 or ep == epochs - 1):
+                rec["val"] = float(np.mean((self.predict(Xval) - Yval) ** 2))
+            hist.append(rec)
+            if log and (ep % 50 == 49 or ep == epochs - 1):
+                log(str(rec))
+        return hist
+
+    def predict(self, X):
+        torch = self.torch
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        out = np.empty((len(X), DIMS[-1]), dtype=np.float32)
+        for lo in range(0, len(X), self.batch):
+            chunk = X[lo:lo + self.batch]
+            xd = torch.from_numpy(chunk).cuda()
+            yd = torch.empty((len(chunk), DIMS[-1]), dtype=torch.float32, device="cuda")
+            self.net.forward(xd.data_ptr(), len(chunk), yd.data_ptr())
+            out[lo:lo + len(chunk)] = yd.cpu().numpy()
+        return out
+
+    def params(self):
+        return self.net.params()
+
+    def load(self, flat):
+        self.net.set_params(flat)
+
+
+def warm_start(solver, cfg, surrogate):
+    """Initialise a run from the surrogate's prediction for its parameters."""
+    y = surrogate.predict(features([cfg]))[0]
+    profile, g_pe, g_see = decode(y, cfg["ey"])
+    solver.warm_start(profile, cfg["t_se_ev"], step=0)
+    return profile
+
+
+def time_to_saturation(solver, window_s=50e-12, rtol=1e-3, t_max=5e-9, check_steps=500):
+    """Step until the Section 2 test holds; returns (saturated, steps, wall s)."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        solver.step(check_steps)
+        steps += check_steps
+        if solver.saturated(window_s, rtol):
+            torch.cuda.synchronize()
+            return True, steps, time.perf_counter() - t0
+        if steps * solver.dt >= t_max:
+            torch.cuda.synchronize()
+            return False, steps, time.perf_counter() - t0
