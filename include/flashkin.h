@@ -190,10 +190,11 @@ int fk_read_trace(fk_ctx* ctx, fk_state* dst, size_t cap, size_t* n_out);
 int fk_write_state(fk_ctx* ctx, const void* f, int src_on_device, double sigma, double sigma_lo,
                    int64_t step);
 
-/* The x-resolved enclosed charge sigma_enc(x) = 2 eps0 E_x(x) (equal to
- * sigma at the dielectric) of the current state at npts >= 2 uniform points
- * x_p = p L / (npts - 1), piecewise linear between the cell centres; into
- * out (host, or device if dst_on_device). */
+/* The x-resolved enclosed charge of the current state,
+ * sigma_enc(x) = sigma - 2 e int_0^x n_e(x') dx' with n_e constant over each
+ * cell (2 eps0 times the self field of the Section 2 field solve; equal to
+ * sigma at the dielectric), at npts >= 2 uniform points x_p = p L / (npts - 1);
+ * into out (host, or device if dst_on_device).  FK_E_INVALID for npts < 2. */
 int fk_read_profile(fk_ctx* ctx, int npts, double* out, int dst_on_device);
 
 /* Warm start from a predicted profile (npts >= 2 values of sigma_enc at the

@@ -156,26 +156,23 @@ __global__ void __launch_bounds__(kFieldThreads) k_field(FieldArgs a)
 // Value of the x-resolved enclosed charge sigma_enc(x) = 2 eps0 E_x(x),
 // piecewise linear through (0, sigma), the cell centres (x_k, 2 eps0 E_x,k)
 // and flat beyond the last centre.
-__device__ double enclosed_at(const double* ex, double sigma, int nx, double dx, double x)
-{
-    if (x <= 0.5 * dx) {
-        const double s1 = 2.0 * kEps0 * ex[0];
-        return sigma + (s1 - sigma) * (x / (0.5 * dx));
-    }
-    const double u = x / dx - 0.5;
-    int k = (int)floor(u);
-    if (k >= nx - 1) return 2.0 * kEps0 * ex[nx - 1];
-    const double w = u - k;
-    return 2.0 * kEps0 * ((1.0 - w) * ex[k] + w * ex[k + 1]);
-}
-
-__global__ void k_profile(const double* __restrict__ ex, const DevState* __restrict__ st, int nx, double dx,
+// Enclosed charge sigma_enc(x) = sigma - 2 e int_0^x n_e dx' (2 eps0 times the
+// self field of the 1D Gauss solve, Section 2) with n_e constant over each
+// cell, at npts uniform points x_p = L p / (npts - 1).  One thread per point
+// sums the cells below it in order.
+__global__ void k_profile(const double* __restrict__ ne, const DevState* __restrict__ st, int nx, double dx,
                           double length, int npts, double* __restrict__ out)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npts) return;
     const double x = length * p / (npts - 1);
-    out[p] = enclosed_at(ex, st->sigma + st->sigma_lo, nx, dx, x);
+    int k = (int)floor(x / dx);
+    k = max(0, min(k, nx));
+    double below = 0.0;
+    for (int q = 0; q < k; ++q) below += ne[q];
+    double s = (st->sigma + st->sigma_lo) - 2.0 * kE * dx * below;
+    if (k < nx) s -= 2.0 * kE * ne[k] * (x - k * dx);
+    out[p] = s;
 }
 
 // Piecewise-linear interpolation of a profile given at npts uniform points.
@@ -1286,16 +1283,18 @@ extern "C" int fk_batch_create(const fk_params* params, int n, void* stream, int
     if (!b) return set_error(nullptr, FK_E_OOM, "host allocation failed");
     b->stream = static_cast<hipStream_t>(stream);
     int rc = FK_OK;
-    if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) rc = FK_E_HIP;
-    if (!rc && hipMalloc(&b->d_counter, sizeof(int)) != hipSuccess) rc = FK_E_OOM;
-    if (!rc && hipMemset(b->d_counter, 0, sizeof(int)) != hipSuccess) rc = FK_E_HIP;
+    hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) rc = bfail(b, e, "hipStreamCreateWithFlags");
+    if (!rc && (e = hipMalloc(&b->d_counter, sizeof(int))) != hipSuccess) rc = bfail(b, e, "hipMalloc");
+    if (!rc && (e = hipMemset(b->d_counter, 0, sizeof(int))) != hipSuccess) rc = bfail(b, e, "hipMemset");
     for (int m = 0; m < n && !rc; ++m) {
         fk_params q = params[m];
         q.tile_rows = b->ti;
         if (q.tile_planes == 0) q.tile_planes = 32;
         fk_ctx* c = nullptr;
         rc = create_impl(&q, stream, nullptr, nullptr, &c, true);
-        if (!rc) b->inst.push_back(c);
+        if (rc) b->err = "instance " + std::to_string(m) + ": " + global_error();
+        else b->inst.push_back(c);
     }
     if (!rc) rc = batch_build(b, 0);
     if (!rc && autotune) {
@@ -1428,7 +1427,7 @@ extern "C" int fk_read_profile(fk_ctx* c, int npts, double* out, int dst_on_devi
         FK_HIP(c, hipMalloc(&tmp, (size_t)npts * sizeof(double)));
         d = tmp;
     }
-    hipLaunchKernelGGL(k_profile, dim3((npts + 255) / 256), dim3(256), 0, c->stream, c->b.ex, c->b.st, c->p.nx,
+    hipLaunchKernelGGL(k_profile, dim3((npts + 255) / 256), dim3(256), 0, c->stream, c->b.ne, c->b.st, c->p.nx,
                        c->L.dx, c->p.length_m, npts, d);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && tmp) e = hipMemcpyAsync(out, tmp, (size_t)npts * sizeof(double), hipMemcpyDeviceToHost, c->stream);

@@ -11,6 +11,16 @@ import os
 
 import numpy as np
 
+# One HIP runtime per process.  torch's HIP libraries ask for the runtime
+# under a different file name than this library does, so whichever loads
+# second would otherwise bring in a second runtime, and only one of the two
+# can open the device.  Loading torch first lets the library bind to torch's
+# runtime, the one that owns the device memory and streams handed over.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    torch = None
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libflashkin.so")
 if not os.path.exists(LIB_PATH):

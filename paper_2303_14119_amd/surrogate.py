@@ -112,6 +112,8 @@ def generate(n_runs, seed, per_batch=64, t_max=3e-9, stream=None, log=None, retr
     attempt = 0
     while todo:
         again = []
+        # runs of similar step count share a batch, so few are left running alone
+        todo.sort(key=lambda c: fk.validate(fk.make_params(c))["dt"])
         for b0 in range(0, len(todo), per_batch):
             cfgs = todo[b0:b0 + per_batch]
             # record about every picosecond of each instance's own time
