@@ -32,8 +32,10 @@ PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "sweep_c1_rocprof.md")
 
 
 def kernel_source_digest():
+    """Hash of the sweep kernel's device code and of the layout rules that
+    shape its launch (tile rows, planes, workgroup size)."""
     h = hashlib.sha256()
-    for name in ("fk_internal.h", "fk_kernels.h", "fk_sweep_fast.h", "fk_solver.hip"):
+    for name in ("fk_internal.h", "fk_kernels.h", "fk_sweep_fast.h", "fk_host.cpp"):
         with open(os.path.join(ROOT, "paper_2303_14119_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -112,26 +112,6 @@ __global__ void __launch_bounds__(kFieldThreads) k_tables_norm(TableArgs a)
 
 // ---------------------------------------------------------------- kernels
 
-// Tiles of a launch: blockIdx -> (x chunk, entry of the launch's v_x tile
-// list), remapped so each XCD takes a contiguous range.
-template <typename T, int TI, int MAXB>
-__global__ void __launch_bounds__(MAXB) k_sweep(SweepArgs<T> a)
-{
-    extern __shared__ double smem[];
-    const int wg = xcd_remap(blockIdx.x, gridDim.x);
-    const int it = a.tile_list[wg % a.n_list];
-    sweep_fast_dispatch<T, TI>(a, it, wg / a.n_list, smem, threadIdx.x, blockDim.x);
-}
-
-template <typename T, int TI, int MAXB>
-__global__ void __launch_bounds__(MAXB) k_sweep_generic(SweepArgs<T> a)
-{
-    extern __shared__ double smem[];
-    const int wg = xcd_remap(blockIdx.x, gridDim.x);
-    const int it = a.tile_list[wg % a.n_list];
-    sweep_body<T, TI, true>(a, it, wg / a.n_list, smem, threadIdx.x, blockDim.x);
-}
-
 template <typename T, int TI>
 __global__ void __launch_bounds__(1024) k_moments(SweepArgs<T> a)
 {

@@ -249,6 +249,26 @@ __device__ __forceinline__ void sweep_any(const SweepArgs<T>& a, int it, int kci
     else sweep_body<T, TI, true>(a, it, kci, smem, j, B);
 }
 
+// Tiles of a launch: blockIdx -> (x chunk, entry of the launch's v_x tile
+// list), remapped so each XCD takes a contiguous range.
+template <typename T, int TI, int MAXB>
+__global__ void __launch_bounds__(MAXB) k_sweep(SweepArgs<T> a)
+{
+    extern __shared__ double smem[];
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int it = a.tile_list[wg % a.n_list];
+    sweep_fast_dispatch<T, TI>(a, it, wg / a.n_list, smem, threadIdx.x, blockDim.x);
+}
+
+template <typename T, int TI, int MAXB>
+__global__ void __launch_bounds__(MAXB) k_sweep_generic(SweepArgs<T> a)
+{
+    extern __shared__ double smem[];
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int it = a.tile_list[wg % a.n_list];
+    sweep_body<T, TI, true>(a, it, wg / a.n_list, smem, threadIdx.x, blockDim.x);
+}
+
 // A sub-tile slot of a batched workgroup with no tile: take part in the same
 // number of workgroup barriers as a tile of nplanes x planes.
 __device__ __forceinline__ void sweep_idle(int nplanes)
