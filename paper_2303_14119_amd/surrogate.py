@@ -237,3 +237,36 @@ def time_to_saturation(solver, window_s=50e-12, rtol=1e-3, t_max=5e-9, check_ste
         if steps * solver.dt >= t_max:
             torch.cuda.synchronize()
             return False, steps, time.perf_counter() - t0
+
+
+def _raw(cfgs):
+    keys = ("ey", "delta_max", "a_max_ev", "t_se_ev", "length", "nx", "nvx", "nvy", "dt")
+    return np.array([[c[k] for k in keys] for c in cfgs], dtype=np.float64)
+
+
+def main(argv=None):
+    """Command line: ``generate`` saturated runs into an .npz file."""
+    import argparse
+    import torch
+    ap = argparse.ArgumentParser(prog="python -m paper_2303_14119_amd.surrogate")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    g = sub.add_parser("generate", help="run the batched solver to saturation and store (X, Y)")
+    g.add_argument("--n", type=int, required=True)
+    g.add_argument("--seed", type=int, required=True)
+    g.add_argument("--per-batch", type=int, default=128)
+    g.add_argument("--t-max", type=float, default=3e-9)
+    g.add_argument("--out", required=True)
+    args = ap.parse_args(argv)
+    torch.cuda.init()
+    stream = torch.cuda.current_stream().cuda_stream
+    if args.cmd == "generate":
+        cfgs, X, Y, sat, wall, failed = generate(args.n, args.seed, per_batch=args.per_batch, t_max=args.t_max,
+                                                 stream=stream, log=lambda m: print(m, flush=True))
+        cells = sum(c["nx"] * c["nvx"] * c["nvy"] for c in cfgs)
+        np.savez(args.out, X=X, Y=Y, sat=sat, raw=_raw(cfgs), wall=wall, n_failed=len(failed))
+        print(f"generated {len(cfgs)} runs ({int(sat.sum())} saturated, {len(failed)} failed) "
+              f"in {wall:.1f} s; {cells / 1e9:.2f} Gcells", flush=True)
+
+
+if __name__ == "__main__":
+    main()
