@@ -977,16 +977,20 @@ extern "C" int fk_autotune(fk_ctx* c, int trial_steps, fk_info* chosen)
 
 // ================================================================ batch
 //
-// Independent instances of uneven sizes advanced together: one persistent
-// sweep launch per step pulls (instance, x chunk, group of v_x tiles) work
-// items from an atomic counter, largest first; a workgroup of 256 threads
-// runs 256 / block tiles of one item side by side.  The reductions and field
-// solves of all instances follow as one launch each.  The three launches of
-// a step are replayed from captured HIP graphs.
+// Independent instances of uneven sizes advanced together.  Each step runs
+// two persistent sweep launches, one over the tiles that take the fast body
+// and one over the rest (ragged or straddling v_x = 0), so each kernel is
+// compiled for one body and keeps its own register budget.  Workgroups pull
+// (instance, x chunk, up to 256 / block v_x tiles) work items from an
+// atomic counter, largest first, and run the item's tiles side by side.
+// The reductions and field solves of all instances follow as one launch
+// each; the three or four launches of a step are replayed from captured
+// HIP graphs.
 
 namespace fk {
 
 constexpr int kBatchThreads = 256;
+constexpr int kBatchMaxGroup = kBatchThreads / 64;
 
 struct BatchInst {
     SweepArgs<float> sw[2];   // from buffer 0 / from buffer 1
@@ -996,12 +1000,13 @@ struct BatchInst {
 };
 
 struct BatchItem {
-    int inst, it0, ntiles, kci;
+    int inst, kci, ntiles;
+    int tile[kBatchMaxGroup];
 };
 
 // sched 0: items taken from an atomic counter (dynamic); sched 1: workgroup
 // w takes items w, w + grid, ... of the cost-sorted list (static).
-template <int TI>
+template <int TI, bool FAST>
 __global__ void __launch_bounds__(kBatchThreads) k_batch_sweep(const BatchInst* __restrict__ insts,
                                                                const BatchItem* __restrict__ items,
                                                                int n_items, int* __restrict__ counter, int from,
@@ -1017,17 +1022,25 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_sweep(const BatchInst* 
         const int m = sched == 0 ? __builtin_amdgcn_readfirstlane(next) : (int)blockIdx.x + round * (int)gridDim.x;
         __syncthreads();
         if (m >= n_items) break;
-        const BatchItem item = items[m];
+        const BatchItem& item = items[m];
         const BatchInst* in = insts + item.inst;
-        const int B = in->block;
-        const int sub = threadIdx.x / B;
-        const int j = threadIdx.x - sub * B;
-        const int k0 = item.kci * in->kc;
+        // B is a multiple of 64, so a wavefront lies in one sub-tile slot:
+        // the slot, its tile and everything derived from them are uniform
+        // per wave and stay in scalar registers
+        const int B = __builtin_amdgcn_readfirstlane(in->block);
+        const int sub = __builtin_amdgcn_readfirstlane((int)threadIdx.x / B);
+        const int j = (int)threadIdx.x - sub * B;
+        const int kci = __builtin_amdgcn_readfirstlane(item.kci);
+        const int k0 = kci * in->kc;
         const int np = min(in->kc, in->nx - k0);
-        if (sub < item.ntiles)
-            sweep_any<float, TI>(in->sw[from], item.it0 + sub, item.kci, smem + (size_t)sub * in->lds_doubles, j, B);
-        else
+        if (sub < __builtin_amdgcn_readfirstlane(item.ntiles)) {
+            const int it = __builtin_amdgcn_readfirstlane(item.tile[sub]);
+            double* slot = smem + (size_t)sub * in->lds_doubles;
+            if (FAST) sweep_fast_dispatch<float, TI>(in->sw[from], it, kci, slot, j, B);
+            else sweep_body<float, TI, true>(in->sw[from], it, kci, slot, j, B);
+        } else {
             sweep_idle(np);
+        }
     }
 }
 
@@ -1037,13 +1050,16 @@ __global__ void __launch_bounds__(256) k_batch_reduce(const BatchInst* __restric
     reduce_tiles(insts[blockIdx.y].rd, sh);
 }
 
-__global__ void __launch_bounds__(kFieldThreads) k_batch_field(const BatchInst* __restrict__ insts, int* counter, int advance)
+// counters[0..1]: the two sweep launches' work counters, cleared for the
+// next step once the sweeps of this one have finished
+__global__ void __launch_bounds__(kFieldThreads) k_batch_field(const BatchInst* __restrict__ insts, int* counters,
+                                                               int advance)
 {
     __shared__ double sh[2 * kFieldThreads];
     FieldArgs a = insts[blockIdx.x].fd;
     a.advance = advance;
     field_block(a, sh);
-    if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;   // the sweep of this step has finished
+    if (blockIdx.x == 0 && threadIdx.x < 2) counters[threadIdx.x] = 0;
 }
 
 }  // namespace fk
@@ -1060,11 +1076,13 @@ struct fk_batch {
     int grid = 0;
     size_t lds = 0;
     int max_blocks_x = 1;
+    int grid_generic = 0;
     std::vector<BatchInst> inst_host;
-    std::vector<BatchItem> items_host;
+    std::vector<BatchItem> items_host;   // fast-body items, then generic ones
+    int n_fast = 0, n_generic = 0;
     BatchInst* d_inst = nullptr;
     BatchItem* d_items = nullptr;
-    int* d_counter = nullptr;
+    int* d_counter = nullptr;           // [2]: fast and generic sweep counters
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     int graph_steps = 8;
     int cur = 0;
@@ -1092,26 +1110,42 @@ size_t batch_slice_doubles(int ti, int block, int kc)
     return (bytes + 7) / 8;
 }
 
+template <int TI>
+void batch_launch_sweeps(const fk_batch* b, int from, hipStream_t s)
+{
+    if (b->n_fast > 0)
+        hipLaunchKernelGGL((k_batch_sweep<TI, true>), dim3(b->grid), dim3(kBatchThreads), b->lds, s, b->d_inst,
+                           b->d_items, b->n_fast, b->d_counter, from, b->sched);
+    if (b->n_generic > 0)
+        hipLaunchKernelGGL((k_batch_sweep<TI, false>), dim3(b->grid_generic), dim3(kBatchThreads), b->lds, s,
+                           b->d_inst, b->d_items + b->n_fast, b->n_generic, b->d_counter + 1, from, b->sched);
+}
+
 void batch_launch_step(const fk_batch* b, int from, hipStream_t s)
 {
-    const size_t n_items = b->items_host.size();
-    if (b->ti == 4)
-        hipLaunchKernelGGL(k_batch_sweep<4>, dim3(b->grid), dim3(kBatchThreads), b->lds, s, b->d_inst, b->d_items,
-                           (int)n_items, b->d_counter, from, b->sched);
-    else
-        hipLaunchKernelGGL(k_batch_sweep<8>, dim3(b->grid), dim3(kBatchThreads), b->lds, s, b->d_inst, b->d_items,
-                           (int)n_items, b->d_counter, from, b->sched);
+    if (b->ti == 4) batch_launch_sweeps<4>(b, from, s);
+    else batch_launch_sweeps<8>(b, from, s);
     hipLaunchKernelGGL(k_batch_reduce, dim3(b->max_blocks_x, b->n_active), dim3(256), 0, s, b->d_inst);
     hipLaunchKernelGGL(k_batch_field, dim3(b->n_active), dim3(kFieldThreads), 0, s, b->d_inst, b->d_counter, 1);
 }
 
-// (Re)build the instance descriptors and the work list for the members'
+template <int TI, bool FAST>
+int batch_occupancy(int* occ, size_t lds)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_batch_sweep<TI, FAST>, kBatchThreads, lds) ==
+                   hipSuccess
+               ? FK_OK
+               : FK_E_HIP;
+}
+
+// (Re)build the instance descriptors and the work lists for the members'
 // current tiling, and capture the step graphs.
 int batch_build(fk_batch* b, int wgs_per_cu)
 {
     FK_BHIP(b, hipStreamSynchronize(b->stream));
     b->inst_host.clear();
     b->items_host.clear();
+    b->n_fast = b->n_generic = 0;
     b->lds = 0;
     b->max_blocks_x = 1;
     b->occ = wgs_per_cu;
@@ -1121,8 +1155,8 @@ int batch_build(fk_batch* b, int wgs_per_cu)
         if (b->active[m]) compact.push_back((int)m);
     b->n_active = (int)compact.size();
     if (b->n_active == 0) return FK_OK;
+    std::vector<BatchItem> fast, generic;
     for (size_t q = 0; q < compact.size(); ++q) {
-        const size_t m = q;
         fk_ctx* c = b->inst[compact[q]];
         BatchInst d{};
         d.sw[0] = sweep_args<float>(c, 0);
@@ -1138,26 +1172,45 @@ int batch_build(fk_batch* b, int wgs_per_cu)
         d.rd.nwg = c->L.nwg;
         d.fd = field_args(c, 1);
         d.block = c->L.block;
-        d.group = kBatchThreads / c->L.block;
+        d.group = std::min(kBatchMaxGroup, kBatchThreads / c->L.block);
         d.kc = c->L.kc;
         d.nx = c->p.nx;
         d.lds_doubles = (int)batch_slice_doubles(b->ti, c->L.block, c->L.kc);
         b->lds = std::max(b->lds, (size_t)d.group * d.lds_doubles * 8);
         b->max_blocks_x = std::max(b->max_blocks_x, (c->p.nx + 255) / 256);
         b->inst_host.push_back(d);
+        // tiles by body, in groups of d.group for every x chunk
+        std::vector<int> tf, tg;
+        for (int it = 0; it < c->L.n_it; ++it)
+            (tile_is_fast(it, b->ti, c->p.nvx) ? tf : tg).push_back(it);
         for (int kci = 0; kci < c->L.n_kc; ++kci)
-            for (int it0 = 0; it0 < c->L.n_it; it0 += d.group)
-                b->items_host.push_back({(int)m, it0, std::min(d.group, c->L.n_it - it0), kci});
+            for (int cls = 0; cls < 2; ++cls) {
+                const std::vector<int>& t = cls == 0 ? tf : tg;
+                for (size_t g0 = 0; g0 < t.size(); g0 += d.group) {
+                    BatchItem it{};
+                    it.inst = (int)q;
+                    it.kci = kci;
+                    it.ntiles = (int)std::min(t.size() - g0, (size_t)d.group);
+                    for (int u = 0; u < it.ntiles; ++u) it.tile[u] = t[g0 + u];
+                    (cls == 0 ? fast : generic).push_back(it);
+                }
+            }
     }
     // largest items first
-    std::stable_sort(b->items_host.begin(), b->items_host.end(), [&](const BatchItem& x, const BatchItem& y) {
+    auto by_cost = [&](const BatchItem& x, const BatchItem& y) {
         auto cost = [&](const BatchItem& t) {
             const fk_ctx* c = b->inst[compact[t.inst]];
             const int np = std::min(c->L.kc, c->p.nx - t.kci * c->L.kc);
             return (double)t.ntiles * np * c->p.nvy;
         };
         return cost(x) > cost(y);
-    });
+    };
+    std::stable_sort(fast.begin(), fast.end(), by_cost);
+    std::stable_sort(generic.begin(), generic.end(), by_cost);
+    b->n_fast = (int)fast.size();
+    b->n_generic = (int)generic.size();
+    b->items_host = fast;
+    b->items_host.insert(b->items_host.end(), generic.begin(), generic.end());
     if (b->d_inst) (void)hipFree(b->d_inst);
     if (b->d_items) (void)hipFree(b->d_items);
     b->d_inst = nullptr;
@@ -1166,17 +1219,17 @@ int batch_build(fk_batch* b, int wgs_per_cu)
     FK_BHIP(b, hipMalloc(&b->d_items, sizeof(BatchItem) * b->items_host.size()));
     FK_BHIP(b, hipMemcpy(b->d_inst, b->inst_host.data(), sizeof(BatchInst) * b->inst_host.size(), hipMemcpyHostToDevice));
     FK_BHIP(b, hipMemcpy(b->d_items, b->items_host.data(), sizeof(BatchItem) * b->items_host.size(), hipMemcpyHostToDevice));
-    // persistent grid: every compute unit holds wgs_per_cu workgroups
-    int dev = 0, cus = 0, occ = 0;
+    // persistent grids: every compute unit holds wgs_per_cu workgroups (or
+    // as many as fit), at most one per item
+    int dev = 0, cus = 0, occ_f = 0, occ_g = 0;
     FK_BHIP(b, hipGetDevice(&dev));
     FK_BHIP(b, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    if (b->ti == 4)
-        FK_BHIP(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_sweep<4>, kBatchThreads, b->lds));
-    else
-        FK_BHIP(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_sweep<8>, kBatchThreads, b->lds));
-    if (occ < 1) return set_error(&b->err, FK_E_INVALID, "batch tiles need more LDS than a compute unit has");
-    const int per_cu = wgs_per_cu > 0 ? std::min(wgs_per_cu, occ) : occ;
-    b->grid = cus * per_cu;
+    int rc = b->ti == 4 ? batch_occupancy<4, true>(&occ_f, b->lds) : batch_occupancy<8, true>(&occ_f, b->lds);
+    if (!rc) rc = b->ti == 4 ? batch_occupancy<4, false>(&occ_g, b->lds) : batch_occupancy<8, false>(&occ_g, b->lds);
+    if (rc) return set_error(&b->err, rc, "hipOccupancyMaxActiveBlocksPerMultiprocessor failed");
+    if (occ_f < 1 || occ_g < 1) return set_error(&b->err, FK_E_INVALID, "batch tiles need more LDS than a compute unit has");
+    b->grid = std::max(1, std::min(cus * (wgs_per_cu > 0 ? std::min(wgs_per_cu, occ_f) : occ_f), b->n_fast));
+    b->grid_generic = std::max(1, std::min(cus * occ_g, b->n_generic));
     // graphs of graph_steps steps from either buffer
     for (auto& g : b->graph)
         if (g) {
@@ -1265,8 +1318,8 @@ extern "C" int fk_batch_create(const fk_params* params, int n, void* stream, int
     int rc = FK_OK;
     hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) rc = bfail(b, e, "hipStreamCreateWithFlags");
-    if (!rc && (e = hipMalloc(&b->d_counter, sizeof(int))) != hipSuccess) rc = bfail(b, e, "hipMalloc");
-    if (!rc && (e = hipMemset(b->d_counter, 0, sizeof(int))) != hipSuccess) rc = bfail(b, e, "hipMemset");
+    if (!rc && (e = hipMalloc(&b->d_counter, 2 * sizeof(int))) != hipSuccess) rc = bfail(b, e, "hipMalloc");
+    if (!rc && (e = hipMemset(b->d_counter, 0, 2 * sizeof(int))) != hipSuccess) rc = bfail(b, e, "hipMemset");
     for (int m = 0; m < n && !rc; ++m) {
         fk_params q = params[m];
         q.tile_rows = b->ti;
@@ -1286,7 +1339,7 @@ extern "C" int fk_batch_create(const fk_params* params, int n, void* stream, int
         float best_ms = 1e30f;
         const int tis[2] = {4, 8};
         const int kcs[3] = {16, 32, 64};
-        const int occs[3] = {2, 3, 0};
+        const int occs[5] = {2, 3, 4, 6, 0};
         for (int ti : tis)
             for (int kc : kcs)
                 for (int occ : occs)

@@ -13,6 +13,7 @@ data, fk_read_profile resamples it, the network trains with fk_mlp_* and
 fk_warm_start builds the initial state.  This module only moves arrays
 between them (torch holds the device buffers).
 """
+import json
 import math
 import time
 
@@ -94,19 +95,25 @@ def run_to_saturation(batch, cfgs, window_s=50e-12, rtol=1e-3, t_max=3e-9, check
     return done
 
 
-def generate(n_runs, seed, per_batch=64, t_max=3e-9, stream=None, log=None, retries=2):
+def generate(n_runs, seed, per_batch=64, t_max=3e-9, stream=None, log=None, retries=0, draw=None):
     """n_runs runs drawn like the batched sweep (seeded), each advanced to
-    saturation or t_max.  The step follows the CFL conditions of Section 2,
-    but it is fixed before the surface charge exists: a run whose self field
-    later drives the v_x Courant number above one is flagged by the library
-    and run again from the start at half the step (at most ``retries``
-    times).  Returns (cfgs, X features, Y targets, saturated flags, wall
-    seconds, failed) where failed lists (cfg, message) of runs still flagged
-    after the retries; those are left out of X and Y."""
+    saturation or t_max.  Returns (cfgs, X features, Y targets, saturated
+    flags, wall seconds, failed) where failed lists (cfg, message) of runs
+    the library flagged; those are left out of X and Y.
+
+    A flagged run is one whose avalanche outgrows the grid: the electron
+    cloud's space charge drives the v_x Courant number past one and the
+    explicit scheme then diverges.  A smaller step only delays this (the
+    step is fixed before the surface charges, Section 2 leaves it to the CFL
+    conditions), so by default flagged runs are not repeated; ``retries``
+    re-runs them from the start at half the step that many times.
+    ``draw(seed, n)`` returns n run dictionaries (default: the batched
+    sweep's distribution)."""
+    draw = draw or (lambda sd, n: W.c2_instances(seed=sd, n=n))
     rng = np.random.default_rng(seed)
     todo = []
     for b0 in range(0, n_runs, per_batch):
-        todo += W.c2_instances(seed=int(rng.integers(1 << 31)), n=min(per_batch, n_runs - b0))
+        todo += draw(int(rng.integers(1 << 31)), min(per_batch, n_runs - b0))
     cfgs_all, xs, ys, sat, failed = [], [], [], [], []
     t0 = time.perf_counter()
     attempt = 0
@@ -244,8 +251,87 @@ def _raw(cfgs):
     return np.array([[c[k] for k in keys] for c in cfgs], dtype=np.float64)
 
 
+def load_data(paths, saturated_only=True):
+    """Concatenate generated .npz files; by default only the runs that
+    reached the Section 2 saturation test."""
+    xs, ys, raws = [], [], []
+    for p in paths:
+        d = np.load(p)
+        keep = d["sat"].astype(bool) if saturated_only else np.ones(len(d["X"]), dtype=bool)
+        xs.append(d["X"][keep])
+        ys.append(d["Y"][keep])
+        raws.append(d["raw"][keep])
+    return np.concatenate(xs), np.concatenate(ys), np.concatenate(raws)
+
+
+def profile_errors(y_pred, y_true, raw):
+    """Per run: relative L2 of the decoded sigma_enc profile and relative
+    errors of the two fluxes."""
+    out = []
+    for yp, yt, r in zip(y_pred, y_true, raw):
+        pp, gp, sp = decode(yp, r[0])
+        pt, gt, st = decode(yt, r[0])
+        out.append((np.linalg.norm(pp - pt) / max(np.linalg.norm(pt), 1e-300), abs(gp / gt - 1), abs(sp / st - 1)))
+    return np.array(out)
+
+
+def train_cli(args, stream):
+    X, Y, raw = load_data(args.data)
+    Xv, Yv, rawv = load_data([args.val])
+    print(f"train {len(X)} saturated runs, held out {len(Xv)}", flush=True)
+    sur = Surrogate(seed=args.seed, stream=stream)
+    t0 = time.perf_counter()
+    hist = sur.fit(X, Y, epochs=args.epochs, lr=args.lr, seed=args.seed, Xval=Xv, Yval=Yv,
+                   log=lambda m: print(m, flush=True))
+    wall = time.perf_counter() - t0
+    pv = sur.predict(Xv)
+    err = profile_errors(pv, Yv, rawv)
+    # the method without the network: the training set's mean target
+    base = profile_errors(np.repeat(Y.mean(axis=0, keepdims=True), len(Yv), axis=0), Yv, rawv)
+    rep = {"train_runs": len(X), "heldout_runs": len(Xv), "epochs": args.epochs, "train_s": wall,
+           "steps": sur.step, "final_train_mse": hist[-1]["train"], "heldout_mse": float(np.mean((pv - Yv) ** 2)),
+           "heldout_profile_rel_l2_median": float(np.median(err[:, 0])),
+           "heldout_profile_rel_l2_p90": float(np.percentile(err[:, 0], 90)),
+           "heldout_gpe_rel_median": float(np.median(err[:, 1])),
+           "heldout_gsee_rel_median": float(np.median(err[:, 2])),
+           "mean_predictor_profile_rel_l2_median": float(np.median(base[:, 0]))}
+    np.savez(args.out, params=sur.params(), dims=np.array(DIMS))
+    print(json.dumps(rep), flush=True)
+
+
+def warmcold_cli(args, stream):
+    cfg = W.c4()
+    sur = Surrogate(stream=stream)
+    sur.load(np.load(args.params)["params"])
+    res = {}
+    profiles = {}
+    for mode in ("cold", "warm"):
+        with fk.Solver(cfg, "f32", stream=stream, trace_cap=8192,
+                       trace_stride=trace_stride(fk.validate(fk.make_params(cfg))["dt"])) as s:
+            if mode == "warm":
+                t0 = time.perf_counter()
+                warm_start(s, cfg, sur)
+                setup = time.perf_counter() - t0
+            else:
+                setup = 0.0
+            sat, steps, wall = time_to_saturation(s, t_max=args.t_max, check_steps=args.check_steps)
+            st = s.state()
+            profiles[mode] = s.profile(NPTS)
+            res[mode] = {"saturated": sat, "steps": steps, "sim_time_s": steps * s.dt, "wall_s": wall,
+                         "setup_s": setup, "sigma": st["sigma"] + st["sigma_lo"], "g_pe": st["g_pe"],
+                         "g_see": st["g_see"]}
+            print(mode, json.dumps(res[mode]), flush=True)
+    d = profiles["warm"] - profiles["cold"]
+    res["final_profile_rel_l2"] = float(np.linalg.norm(d) / np.linalg.norm(profiles["cold"]))
+    res["speedup_wall"] = res["cold"]["wall_s"] / (res["warm"]["wall_s"] + res["warm"]["setup_s"])
+    np.savez(args.out, cold=profiles["cold"], warm=profiles["warm"])
+    print(json.dumps(res), flush=True)
+
+
 def main(argv=None):
-    """Command line: ``generate`` saturated runs into an .npz file."""
+    """Command line: ``generate`` saturated runs into an .npz file, ``train``
+    the network on them, ``warmcold`` compares a warm-started large run with
+    a cold start."""
     import argparse
     import torch
     ap = argparse.ArgumentParser(prog="python -m paper_2303_14119_amd.surrogate")
@@ -256,6 +342,18 @@ def main(argv=None):
     g.add_argument("--per-batch", type=int, default=128)
     g.add_argument("--t-max", type=float, default=3e-9)
     g.add_argument("--out", required=True)
+    t = sub.add_parser("train", help="train the network on generated runs")
+    t.add_argument("--data", nargs="+", required=True)
+    t.add_argument("--val", required=True)
+    t.add_argument("--epochs", type=int, default=400)
+    t.add_argument("--lr", type=float, default=1e-3)
+    t.add_argument("--seed", type=int, default=0)
+    t.add_argument("--out", required=True)
+    w = sub.add_parser("warmcold", help="warm vs cold start on the 4096 x 384 x 384 run")
+    w.add_argument("--params", required=True)
+    w.add_argument("--t-max", type=float, default=5e-9)
+    w.add_argument("--check-steps", type=int, default=500)
+    w.add_argument("--out", required=True)
     args = ap.parse_args(argv)
     torch.cuda.init()
     stream = torch.cuda.current_stream().cuda_stream
@@ -266,6 +364,10 @@ def main(argv=None):
         np.savez(args.out, X=X, Y=Y, sat=sat, raw=_raw(cfgs), wall=wall, n_failed=len(failed))
         print(f"generated {len(cfgs)} runs ({int(sat.sum())} saturated, {len(failed)} failed) "
               f"in {wall:.1f} s; {cells / 1e9:.2f} Gcells", flush=True)
+    elif args.cmd == "train":
+        train_cli(args, stream)
+    else:
+        warmcold_cli(args, stream)
 
 
 if __name__ == "__main__":

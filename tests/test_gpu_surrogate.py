@@ -1,0 +1,75 @@
+"""What the trained network gains over the method without it (GPU).
+
+A small family of coarse runs (128 x 64 x 64 cells) is advanced to
+saturation by the batched solver, the surrogate network is trained on them
+with the library's kernels, and then:
+  * on held-out runs its predicted sigma_enc(x) beats the best constant
+    predictor (the training mean), which is what a run without the network
+    could guess;
+  * a held-out run warm-started from the prediction passes the Section 2
+    saturation test in fewer steps than the cold start, and both runs end
+    at the same state (the cold run is the judge).
+"""
+import numpy as np
+import pytest
+
+from paper_2303_14119_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2303_14119_amd import flashkin, surrogate
+    return torch, flashkin, surrogate
+
+
+def family(seed, n):
+    """Runs near the 128 x 64 x 64 plain run, in a parameter box where the
+    avalanche saturates on this grid (checked against the oracle)."""
+    rng = np.random.default_rng(seed)
+    return [W.config(nx=128, nvx=64, nvy=64, length=float(rng.uniform(0.8e-3, 1.2e-3)),
+                     ey=-float(rng.uniform(3e6, 5e6)), delta_max=float(rng.uniform(2.0, 2.6)),
+                     a_max_ev=float(rng.uniform(350.0, 450.0)), t_se_ev=float(rng.uniform(1.5, 2.5)))
+            for _ in range(n)]
+
+
+def test_network_beats_the_mean_and_warm_start_saves_steps(env):
+    torch, fk, S = env
+    stream = torch.cuda.current_stream().cuda_stream
+    cfgs, X, Y, sat, wall, failed = S.generate(128, seed=7, per_batch=128, t_max=4e-9, stream=stream, draw=family)
+    keep = sat.astype(bool)
+    print("generated", len(cfgs), "saturated", int(keep.sum()), "failed", len(failed), "in", round(wall, 1), "s")
+    assert keep.sum() >= 100
+    X, Y = X[keep], Y[keep]
+    raw = np.array([[c["ey"]] for c, k in zip(cfgs, keep) if k])
+    Xt, Yt, Xv, Yv, rv = X[:-16], Y[:-16], X[-16:], Y[-16:], raw[-16:]
+    sur = S.Surrogate(seed=1, batch=32, stream=stream)
+    hist = sur.fit(Xt, Yt, epochs=250, lr=1e-3, seed=1)
+    assert hist[-1]["train"] < 0.2 * hist[0]["train"]
+    pv = sur.predict(Xv)
+    err = S.profile_errors(pv, Yv, rv)[:, 0]
+    base = S.profile_errors(np.repeat(Yt.mean(axis=0, keepdims=True), len(Yv), axis=0), Yv, rv)[:, 0]
+    print("held-out profile rel L2: network median", np.median(err), "mean predictor median", np.median(base))
+    assert np.median(err) < 0.5 * np.median(base)
+
+    held = [c for c, k in zip(cfgs, keep) if k][-16:]
+    for cfg in held[:2]:
+        steps = {}
+        final = {}
+        for mode in ("cold", "warm"):
+            stride = S.trace_stride(fk.validate(fk.make_params(cfg))["dt"])
+            with fk.Solver(cfg, "f32", stream=stream, trace_cap=8192, trace_stride=stride) as s:
+                if mode == "warm":
+                    S.warm_start(s, cfg, sur)
+                ok, n, _ = S.time_to_saturation(s, t_max=6e-9, check_steps=100)
+                assert ok, mode
+                steps[mode] = n
+                final[mode] = s.profile(S.NPTS)
+        d = np.linalg.norm(final["warm"] - final["cold"]) / np.linalg.norm(final["cold"])
+        print("steps to saturation cold", steps["cold"], "warm", steps["warm"], "final profile rel L2", d)
+        assert steps["warm"] < steps["cold"]
+        assert d < 2e-2
