@@ -76,6 +76,71 @@ def cpu_baseline(cfg, budget_s=12.0):
             "sample": f"{n} whole FP64 steps of the same 2048x256x256 workload ({el:.1f} s)"}
 
 
+def bench_batch(args):
+    """64 uneven instances (seed 0) in one persistent launch per step:
+    Gcell-updates/s over args.steps steps after args.warmup steps."""
+    import torch
+    from paper_2303_14119_amd import flashkin as fk
+    from paper_2303_14119_amd import workloads as W
+    torch.cuda.init()
+    stream = torch.cuda.current_stream().cuda_stream
+    b = fk.Batch(W.c2_instances(seed=0, n=64), stream=stream, trace_cap=16, trace_stride=1000)
+    info = b.info()
+    b.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    # instances whose avalanche outgrows their grid are flagged; the timing
+    # is unaffected, the count is reported
+    flagged = sum(1 for v in b.views if fk.fk_sync(v._h) != 0)
+    b.close()
+    v = info["cells"] * args.steps / el / 1e9
+    print(json.dumps({"mode": "batch", "metric": "Gcell-updates/s", "value": round(v, 3), "steps": args.steps,
+                      "warmup": args.warmup, "ms_per_step": round(el * 1e3 / args.steps, 4),
+                      "hbm_frac_algorithmic": round(8.0 * v * 1e9 / (HBM_PEAK_GBS * 1e9), 4),
+                      "cells": info["cells"], "instances": info["n"], "flagged_instances": flagged,
+                      "tile_rows": info["tile_rows"], "tile_planes": info["tile_planes"]}), flush=True)
+
+
+def bench_mlp(args):
+    """Surrogate training steps (forward, backward, AdamW) at batch 256 on
+    the 5-512-512-512-512-258 network."""
+    import numpy as np
+    import torch
+    from paper_2303_14119_amd import flashkin as fk
+    from paper_2303_14119_amd import surrogate as S
+    torch.cuda.init()
+    stream = torch.cuda.current_stream().cuda_stream
+    dims, m = S.DIMS, 256
+    net = fk.MLP(dims, max_batch=m, stream=stream)
+    net.set_params(S.init_params(dims, 0))
+    rng = np.random.default_rng(0)
+    x = torch.from_numpy(rng.uniform(-1, 1, (m, dims[0])).astype(np.float32)).cuda()
+    t = torch.from_numpy(rng.standard_normal((m, dims[-1])).astype(np.float32)).cuda()
+    flops = sum(2 * m * dims[l] * dims[l + 1] * 3 for l in range(len(dims) - 1))
+    step = 0
+    for _ in range(args.warmup):
+        step += 1
+        net.forward(x.data_ptr(), m)
+        net.backward(t.data_ptr(), m)
+        net.adamw(step)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step += 1
+        net.forward(x.data_ptr(), m)
+        net.backward(t.data_ptr(), m)
+        net.adamw(step)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    net.close()
+    print(json.dumps({"mode": "mlp", "ms_per_step": round(el * 1e3 / args.steps, 4), "steps": args.steps,
+                      "gflop_per_step": round(flops / 1e9, 4), "tflops": round(flops * args.steps / el / 1e12, 3),
+                      "mfma_bf16_peak_tflops": 2500.0}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,11 +151,18 @@ def main():
                     help="steps run before the warmup to drive the state into the avalanche")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (counter calibration)")
+    ap.add_argument("--mode", choices=("c1", "batch", "mlp"), default="c1",
+                    help="c1: the headline line (default); batch: the 64-instance batched sweep; "
+                         "mlp: surrogate training steps (both for profiling, one JSON line each)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); a run over several GPUs "
+              "would split x into slabs exchanging one half-plane per neighbour and step", file=sys.stderr)
         sys.exit(2)
+    if args.mode == "batch":
+        return bench_batch(args)
+    if args.mode == "mlp":
+        return bench_mlp(args)
 
     import torch
     from paper_2303_14119_amd import flashkin as fk

@@ -991,6 +991,12 @@ namespace fk {
 
 constexpr int kBatchThreads = 256;
 constexpr int kBatchMaxGroup = kBatchThreads / 64;
+// Work classes, one sweep launch each: fast or generic body, workgroups of
+// 256 threads (v_y blocks of 64, 128 or 256 lanes: 4, 2 or 1 tiles side by
+// side) or of 192 threads (one tile of a 192-lane block, no idle wave).
+constexpr int kBatchClasses = 4;
+__host__ __device__ constexpr bool class_fast(int k) { return k < 2; }
+__host__ __device__ constexpr int class_threads(int k) { return (k & 1) ? 192 : 256; }
 
 struct BatchInst {
     SweepArgs<float> sw[2];   // from buffer 0 / from buffer 1
@@ -1050,8 +1056,8 @@ __global__ void __launch_bounds__(256) k_batch_reduce(const BatchInst* __restric
     reduce_tiles(insts[blockIdx.y].rd, sh);
 }
 
-// counters[0..1]: the two sweep launches' work counters, cleared for the
-// next step once the sweeps of this one have finished
+// counters[0 .. kBatchClasses-1]: the sweep launches' work counters, cleared
+// for the next step once the sweeps of this one have finished
 __global__ void __launch_bounds__(kFieldThreads) k_batch_field(const BatchInst* __restrict__ insts, int* counters,
                                                                int advance)
 {
@@ -1059,7 +1065,7 @@ __global__ void __launch_bounds__(kFieldThreads) k_batch_field(const BatchInst* 
     FieldArgs a = insts[blockIdx.x].fd;
     a.advance = advance;
     field_block(a, sh);
-    if (blockIdx.x == 0 && threadIdx.x < 2) counters[threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < kBatchClasses) counters[threadIdx.x] = 0;
 }
 
 }  // namespace fk
@@ -1076,13 +1082,12 @@ struct fk_batch {
     int grid = 0;
     size_t lds = 0;
     int max_blocks_x = 1;
-    int grid_generic = 0;
     std::vector<BatchInst> inst_host;
-    std::vector<BatchItem> items_host;   // fast-body items, then generic ones
-    int n_fast = 0, n_generic = 0;
+    std::vector<BatchItem> items_host;   // the classes' items, one range each
+    int cls_off[kBatchClasses] = {0}, cls_n[kBatchClasses] = {0}, cls_grid[kBatchClasses] = {0};
     BatchInst* d_inst = nullptr;
     BatchItem* d_items = nullptr;
-    int* d_counter = nullptr;           // [2]: fast and generic sweep counters
+    int* d_counter = nullptr;           // [kBatchClasses] sweep work counters
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     int graph_steps = 8;
     int cur = 0;
@@ -1113,12 +1118,16 @@ size_t batch_slice_doubles(int ti, int block, int kc)
 template <int TI>
 void batch_launch_sweeps(const fk_batch* b, int from, hipStream_t s)
 {
-    if (b->n_fast > 0)
-        hipLaunchKernelGGL((k_batch_sweep<TI, true>), dim3(b->grid), dim3(kBatchThreads), b->lds, s, b->d_inst,
-                           b->d_items, b->n_fast, b->d_counter, from, b->sched);
-    if (b->n_generic > 0)
-        hipLaunchKernelGGL((k_batch_sweep<TI, false>), dim3(b->grid_generic), dim3(kBatchThreads), b->lds, s,
-                           b->d_inst, b->d_items + b->n_fast, b->n_generic, b->d_counter + 1, from, b->sched);
+    for (int k = 0; k < kBatchClasses; ++k) {
+        if (b->cls_n[k] == 0) continue;
+        const BatchItem* items = b->d_items + b->cls_off[k];
+        if (class_fast(k))
+            hipLaunchKernelGGL((k_batch_sweep<TI, true>), dim3(b->cls_grid[k]), dim3(class_threads(k)), b->lds, s,
+                               b->d_inst, items, b->cls_n[k], b->d_counter + k, from, b->sched);
+        else
+            hipLaunchKernelGGL((k_batch_sweep<TI, false>), dim3(b->cls_grid[k]), dim3(class_threads(k)), b->lds, s,
+                               b->d_inst, items, b->cls_n[k], b->d_counter + k, from, b->sched);
+    }
 }
 
 void batch_launch_step(const fk_batch* b, int from, hipStream_t s)
@@ -1129,13 +1138,17 @@ void batch_launch_step(const fk_batch* b, int from, hipStream_t s)
     hipLaunchKernelGGL(k_batch_field, dim3(b->n_active), dim3(kFieldThreads), 0, s, b->d_inst, b->d_counter, 1);
 }
 
-template <int TI, bool FAST>
-int batch_occupancy(int* occ, size_t lds)
+int batch_occupancy(int ti, int k, size_t lds, int* occ)
 {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_batch_sweep<TI, FAST>, kBatchThreads, lds) ==
-                   hipSuccess
-               ? FK_OK
-               : FK_E_HIP;
+    hipError_t e;
+    const int nt = class_threads(k);
+    if (ti == 4)
+        e = class_fast(k) ? hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_batch_sweep<4, true>, nt, lds)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_batch_sweep<4, false>, nt, lds);
+    else
+        e = class_fast(k) ? hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_batch_sweep<8, true>, nt, lds)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_batch_sweep<8, false>, nt, lds);
+    return e == hipSuccess ? FK_OK : FK_E_HIP;
 }
 
 // (Re)build the instance descriptors and the work lists for the members'
@@ -1145,7 +1158,7 @@ int batch_build(fk_batch* b, int wgs_per_cu)
     FK_BHIP(b, hipStreamSynchronize(b->stream));
     b->inst_host.clear();
     b->items_host.clear();
-    b->n_fast = b->n_generic = 0;
+    for (int k = 0; k < kBatchClasses; ++k) b->cls_off[k] = b->cls_n[k] = b->cls_grid[k] = 0;
     b->lds = 0;
     b->max_blocks_x = 1;
     b->occ = wgs_per_cu;
@@ -1155,7 +1168,7 @@ int batch_build(fk_batch* b, int wgs_per_cu)
         if (b->active[m]) compact.push_back((int)m);
     b->n_active = (int)compact.size();
     if (b->n_active == 0) return FK_OK;
-    std::vector<BatchItem> fast, generic;
+    std::vector<BatchItem> cls[kBatchClasses];
     for (size_t q = 0; q < compact.size(); ++q) {
         fk_ctx* c = b->inst[compact[q]];
         BatchInst d{};
@@ -1183,16 +1196,17 @@ int batch_build(fk_batch* b, int wgs_per_cu)
         std::vector<int> tf, tg;
         for (int it = 0; it < c->L.n_it; ++it)
             (tile_is_fast(it, b->ti, c->p.nvx) ? tf : tg).push_back(it);
+        const int narrow = d.group * d.block == 192 ? 1 : 0;   // 192-thread workgroups
         for (int kci = 0; kci < c->L.n_kc; ++kci)
-            for (int cls = 0; cls < 2; ++cls) {
-                const std::vector<int>& t = cls == 0 ? tf : tg;
+            for (int body = 0; body < 2; ++body) {
+                const std::vector<int>& t = body == 0 ? tf : tg;
                 for (size_t g0 = 0; g0 < t.size(); g0 += d.group) {
                     BatchItem it{};
                     it.inst = (int)q;
                     it.kci = kci;
                     it.ntiles = (int)std::min(t.size() - g0, (size_t)d.group);
                     for (int u = 0; u < it.ntiles; ++u) it.tile[u] = t[g0 + u];
-                    (cls == 0 ? fast : generic).push_back(it);
+                    cls[2 * body + narrow].push_back(it);
                 }
             }
     }
@@ -1205,12 +1219,12 @@ int batch_build(fk_batch* b, int wgs_per_cu)
         };
         return cost(x) > cost(y);
     };
-    std::stable_sort(fast.begin(), fast.end(), by_cost);
-    std::stable_sort(generic.begin(), generic.end(), by_cost);
-    b->n_fast = (int)fast.size();
-    b->n_generic = (int)generic.size();
-    b->items_host = fast;
-    b->items_host.insert(b->items_host.end(), generic.begin(), generic.end());
+    for (int k = 0; k < kBatchClasses; ++k) {
+        std::stable_sort(cls[k].begin(), cls[k].end(), by_cost);
+        b->cls_off[k] = (int)b->items_host.size();
+        b->cls_n[k] = (int)cls[k].size();
+        b->items_host.insert(b->items_host.end(), cls[k].begin(), cls[k].end());
+    }
     if (b->d_inst) (void)hipFree(b->d_inst);
     if (b->d_items) (void)hipFree(b->d_items);
     b->d_inst = nullptr;
@@ -1221,15 +1235,21 @@ int batch_build(fk_batch* b, int wgs_per_cu)
     FK_BHIP(b, hipMemcpy(b->d_items, b->items_host.data(), sizeof(BatchItem) * b->items_host.size(), hipMemcpyHostToDevice));
     // persistent grids: every compute unit holds wgs_per_cu workgroups (or
     // as many as fit), at most one per item
-    int dev = 0, cus = 0, occ_f = 0, occ_g = 0;
+    int dev = 0, cus = 0;
     FK_BHIP(b, hipGetDevice(&dev));
     FK_BHIP(b, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    int rc = b->ti == 4 ? batch_occupancy<4, true>(&occ_f, b->lds) : batch_occupancy<8, true>(&occ_f, b->lds);
-    if (!rc) rc = b->ti == 4 ? batch_occupancy<4, false>(&occ_g, b->lds) : batch_occupancy<8, false>(&occ_g, b->lds);
-    if (rc) return set_error(&b->err, rc, "hipOccupancyMaxActiveBlocksPerMultiprocessor failed");
-    if (occ_f < 1 || occ_g < 1) return set_error(&b->err, FK_E_INVALID, "batch tiles need more LDS than a compute unit has");
-    b->grid = std::max(1, std::min(cus * (wgs_per_cu > 0 ? std::min(wgs_per_cu, occ_f) : occ_f), b->n_fast));
-    b->grid_generic = std::max(1, std::min(cus * occ_g, b->n_generic));
+    b->grid = 0;
+    for (int k = 0; k < kBatchClasses; ++k) {
+        if (b->cls_n[k] == 0) continue;
+        int occ = 0;
+        if (batch_occupancy(b->ti, k, b->lds, &occ))
+            return set_error(&b->err, FK_E_HIP, "hipOccupancyMaxActiveBlocksPerMultiprocessor failed");
+        if (occ < 1) return set_error(&b->err, FK_E_INVALID, "batch tiles need more LDS than a compute unit has");
+        // the fast classes carry the bulk: they take the tuned occupancy
+        const int per_cu = (class_fast(k) && wgs_per_cu > 0) ? std::min(wgs_per_cu, occ) : occ;
+        b->cls_grid[k] = std::max(1, std::min(cus * per_cu, b->cls_n[k]));
+        b->grid = std::max(b->grid, b->cls_grid[k]);
+    }
     // graphs of graph_steps steps from either buffer
     for (auto& g : b->graph)
         if (g) {
@@ -1318,8 +1338,8 @@ extern "C" int fk_batch_create(const fk_params* params, int n, void* stream, int
     int rc = FK_OK;
     hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) rc = bfail(b, e, "hipStreamCreateWithFlags");
-    if (!rc && (e = hipMalloc(&b->d_counter, 2 * sizeof(int))) != hipSuccess) rc = bfail(b, e, "hipMalloc");
-    if (!rc && (e = hipMemset(b->d_counter, 0, 2 * sizeof(int))) != hipSuccess) rc = bfail(b, e, "hipMemset");
+    if (!rc && (e = hipMalloc(&b->d_counter, kBatchClasses * sizeof(int))) != hipSuccess) rc = bfail(b, e, "hipMalloc");
+    if (!rc && (e = hipMemset(b->d_counter, 0, kBatchClasses * sizeof(int))) != hipSuccess) rc = bfail(b, e, "hipMemset");
     for (int m = 0; m < n && !rc; ++m) {
         fk_params q = params[m];
         q.tile_rows = b->ti;
