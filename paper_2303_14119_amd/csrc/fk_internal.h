@@ -66,13 +66,22 @@ __host__ __device__ inline int tile_split(int it, int ti, int nvx)
     return s;
 }
 
-// Whether tile `it` takes the fast body: full (not ragged) and split at
+// Whether tile `it` takes the main launch's fast body: full and split at
 // 0, 1, ti+1 or ti+2.
 __host__ __device__ inline bool tile_is_fast(int it, int ti, int nvx)
 {
     if ((it + 1) * ti > nvx) return false;
     const int s = tile_split(it, ti, nvx);
     return s == 0 || s == 1 || s == ti + 1 || s == ti + 2;
+}
+
+// Of the other tiles, those with a compiled fast body in the second launch:
+// tiles of 4 or 8 rows, full (split inside the tile) or ragged at +v_max
+// with every row at v_x > 0.
+__host__ __device__ inline bool tile_is_special(int it, int ti, int nvx)
+{
+    if ((ti != 4 && ti != 8) || tile_is_fast(it, ti, nvx)) return false;
+    return (it + 1) * ti <= nvx || tile_split(it, ti, nvx) == 0;
 }
 int set_error(std::string* slot, int code, const std::string& msg);
 const char* global_error();

@@ -138,16 +138,21 @@ __global__ void k_mlp_input(const float* __restrict__ x, int M, int d, int pad, 
 }
 
 // MSE loss over the first dout columns and its gradient 2 (y - t) / (M dout)
-// as bf16 in both layouts (padded columns get 0).  One workgroup.
-__global__ void __launch_bounds__(1024) k_mlp_loss(const float* __restrict__ y, int ldy, const float* __restrict__ t,
-                                                   int M, int dout, int pad, __bf16* __restrict__ dz, int lddz,
-                                                   __bf16* __restrict__ dzt, int lddzt, float* __restrict__ loss)
+// as bf16 in both layouts (padded columns get 0).  Workgroup b takes rows
+// [kLossRows b, kLossRows (b + 1)) and writes its sum of squares to part[b].
+constexpr int kLossRows = 4;
+
+__global__ void __launch_bounds__(256) k_mlp_loss(const float* __restrict__ y, int ldy, const float* __restrict__ t,
+                                                  int M, int dout, int pad, __bf16* __restrict__ dz, int lddz,
+                                                  __bf16* __restrict__ dzt, int lddzt, double* __restrict__ part)
 {
-    __shared__ double sh[1024];
+    __shared__ double sh[256];
     const double scale = 1.0 / ((double)M * dout);
+    const int m0 = blockIdx.x * kLossRows;
+    const int rows = min(kLossRows, M - m0);
     double acc = 0.0;
-    for (int idx = threadIdx.x; idx < M * pad; idx += blockDim.x) {
-        const int m = idx / pad, n = idx % pad;
+    for (int idx = threadIdx.x; idx < rows * pad; idx += blockDim.x) {
+        const int m = m0 + idx / pad, n = idx % pad;
         float g = 0.0f;
         if (n < dout) {
             const float r = y[(size_t)m * ldy + n] - t[(size_t)m * dout + n];
@@ -158,6 +163,17 @@ __global__ void __launch_bounds__(1024) k_mlp_loss(const float* __restrict__ y, 
         dz[(size_t)m * lddz + n] = h;
         dzt[(size_t)n * lddzt + m] = h;
     }
+    acc = mlp_block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// loss = scale * sum of the partials, in a fixed order (one workgroup)
+__global__ void __launch_bounds__(256) k_mlp_loss_sum(const double* __restrict__ part, int n, double scale,
+                                                      float* __restrict__ loss)
+{
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += part[i];
     acc = mlp_block_sum(acc, sh);
     if (threadIdx.x == 0) *loss = (float)(acc * scale);
 }
@@ -239,6 +255,7 @@ struct fk_mlp {
     float* z[kMaxLayers + 1];
     __bf16 *dz[kMaxLayers + 1], *dzT[kMaxLayers + 1];
     float* loss = nullptr;
+    double* loss_part = nullptr;         // per-workgroup sums of squares
     std::string err;
 };
 
@@ -299,6 +316,7 @@ extern "C" int fk_mlp_create(int n_layers, const int32_t* dims, int max_batch, v
         need((void**)&n->dz[l], M * n->pad[l] * 2); need((void**)&n->dzT[l], M * n->pad[l] * 2);
     }
     need((void**)&n->loss, 256);
+    need((void**)&n->loss_part, ((M + kLossRows - 1) / kLossRows) * sizeof(double));
     for (auto& q : want) off += (q.second + 255) & ~size_t(255);
     if (hipMalloc(&n->pool, off) != hipSuccess) {
         delete n;
@@ -431,8 +449,11 @@ extern "C" int fk_mlp_backward(fk_mlp* n, const float* target, int M, float* los
     if (!n || !target || M != n->last_m || M % 16)
         return set_error(n ? &n->err : nullptr, FK_E_INVALID, "fk_mlp_backward needs the batch of the last forward (a multiple of 16)");
     const int mb = n->max_batch, L = n->L;
-    hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(1024), 0, n->stream, n->z[L], n->pad[L], target, M, n->dims[L],
-                       n->pad[L], n->dz[L], n->pad[L], n->dzT[L], mb, n->loss);
+    const int loss_blocks = (M + kLossRows - 1) / kLossRows;
+    hipLaunchKernelGGL(k_mlp_loss, dim3(loss_blocks), dim3(256), 0, n->stream, n->z[L], n->pad[L], target, M,
+                       n->dims[L], n->pad[L], n->dz[L], n->pad[L], n->dzT[L], mb, n->loss_part);
+    hipLaunchKernelGGL(k_mlp_loss_sum, dim3(1), dim3(256), 0, n->stream, n->loss_part, loss_blocks,
+                       1.0 / ((double)M * n->dims[L]), n->loss);
     for (int l = L; l >= 1; --l) {
         // weight and bias gradients of layer l (1-based): dW = dZ_l^T A_{l-1}
         GemmArgs g{};

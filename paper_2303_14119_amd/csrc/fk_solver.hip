@@ -1043,7 +1043,7 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_sweep(const BatchInst* 
             const int it = __builtin_amdgcn_readfirstlane(item.tile[sub]);
             double* slot = smem + (size_t)sub * in->lds_doubles;
             if (FAST) sweep_fast_dispatch<float, TI>(in->sw[from], it, kci, slot, j, B);
-            else sweep_body<float, TI, true>(in->sw[from], it, kci, slot, j, B);
+            else sweep_rest<float, TI>(in->sw[from], it, kci, slot, j, B);
         } else {
             sweep_idle(np);
         }

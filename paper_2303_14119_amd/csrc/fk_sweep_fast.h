@@ -2,9 +2,13 @@
 // compile-time row S: rows r < S have v_x <= 0 (their upwind x neighbour is
 // the plane above), rows r >= S have v_x > 0 (upwind is the plane below).
 // Rows are r = 0 .. TI+1 for v_x rows i = i0 - 1 + r (r = 0 and r = TI+1
-// are the halo rows of the v_x sweep).  Used for every tile of a grid
-// whose v_x tiles do not straddle v_x = 0 except at a halo row and whose
-// last tile is full; other tiles take the generic body.
+// are the halo rows of the v_x sweep).
+//
+// Two launches per step: the main one over full tiles split at an edge
+// (S = 0, 1, TI+1, TI+2), which covers almost every tile and keeps the
+// register budget low; the second over the rest, where tiles of 4 or 8 rows
+// split inside the tile or ragged at +v_max still take a compiled fast body
+// and only the remainder takes the generic masked body.
 //
 // Per row the thread keeps the two x planes the upwind update reads plus
 // one prefetched plane.  Rows outside the grid (the halo below the first
@@ -16,7 +20,7 @@
 
 namespace fk {
 
-template <typename T, int TI, int S>
+template <typename T, int TI, int S, bool RAGGED = false>
 __device__ __forceinline__ void sweep_fast(const SweepArgs<T>& a, int it, int kci, double* smem, int j, int B)
 {
     const int i0 = it * TI;
@@ -37,6 +41,12 @@ __device__ __forceinline__ void sweep_fast(const SweepArgs<T>& a, int it, int kc
     const int vb = jok ? i0 * rb + j * es : kIdleLaneOffset;
     const int vlo = (jok && !first) ? (i0 - 1) * rb + j * es : kIdleLaneOffset;
     const int vhi = (jok && !last) ? (i0 + TI) * rb + j * es : kIdleLaneOffset;
+    // a ragged last tile (RAGGED) holds R < TI rows: rows past the grid get
+    // an out-of-range lane offset of their own, so they read 0 and store
+    // nothing
+    const int R = RAGGED ? a.nvx - i0 : TI;
+    const int vb0 = i0 * rb + j * es;
+    auto roff = [&](int r) { return (jok && r <= R) ? vb0 + (r - 1) * rb : kIdleLaneOffset; };
 
     T* xb = reinterpret_cast<T*>(smem);                       // [2][TI][W]
     double* wsum = reinterpret_cast<double*>(xb + 2 * TI * W); // [kc][nw]
@@ -57,6 +67,7 @@ __device__ __forceinline__ void sweep_fast(const SweepArgs<T>& a, int it, int kc
     auto ldrow = [&](const rsrc_t& pr, int r) -> T {
         if (r == 0) return bload<T>(pr, vlo, 0);
         if (r == TI + 1) return bload<T>(pr, vhi, 0);
+        if (RAGGED) return bload<T>(pr, roff(r), 0);
         return bload<T>(pr, vb, (r - 1) * rb);
     };
 
@@ -123,11 +134,22 @@ __device__ __forceinline__ void sweep_fast(const SweepArgs<T>& a, int it, int kc
         if (d > T(0)) {
 #pragma unroll
             for (int r = 1; r <= TI; ++r) f2[r - 1] = f1[r] - d * (f1[r] - f1[r - 1]);
-            if (last) lv += (double)d * (double)f1[TI];          // leaves through +v_max
+            if (RAGGED) {
+#pragma unroll
+                for (int r = 1; r <= TI; ++r)
+                    if (r == R) lv += (double)d * (double)f1[r];  // leaves through +v_max
+            } else if (last) {
+                lv += (double)d * (double)f1[TI];                 // leaves through +v_max
+            }
         } else {
 #pragma unroll
             for (int r = 1; r <= TI; ++r) f2[r - 1] = f1[r] - d * (f1[r + 1] - f1[r]);
             if (first) lv -= (double)d * (double)f1[1];          // leaves through -v_max
+        }
+        if (RAGGED) {
+#pragma unroll
+            for (int r = 1; r <= TI; ++r)
+                if (r > R) f2[r - 1] = T(0);                      // no cells past +v_max
         }
 
         // v_y sweep by a_y: the neighbouring column comes from LDS
@@ -157,13 +179,17 @@ __device__ __forceinline__ void sweep_fast(const SweepArgs<T>& a, int it, int kc
         if (s != 0.0) {
             const T ts = T(s);
 #pragma unroll
-            for (int r = 0; r < TI; ++r) f3[r] += ts * bload<T>(psrc, vb, r * rb);
+            for (int r = 0; r < TI; ++r)
+                f3[r] += ts * (RAGGED ? bload<T>(psrc, roff(r + 1), 0) : bload<T>(psrc, vb, r * rb));
         }
 
         {
             const rsrc_t po = make_rsrc(a.fout + (size_t)k * plane, pbytes);
 #pragma unroll
-            for (int r = 0; r < TI; ++r) bstore<T>(f3[r], po, vb, r * rb);
+            for (int r = 0; r < TI; ++r) {
+                if (RAGGED) bstore<T>(f3[r], po, roff(r + 1), 0);
+                else bstore<T>(f3[r], po, vb, r * rb);
+            }
         }
 
         // moments of f^{n+1}
@@ -241,12 +267,33 @@ __device__ __forceinline__ void sweep_fast_dispatch(const SweepArgs<T>& a, int i
     }
 }
 
-// Any tile: the fast body when the tile qualifies, else the generic one.
-template <typename T, int TI>
-__device__ __forceinline__ void sweep_any(const SweepArgs<T>& a, int it, int kci, double* smem, int j, int B)
+// Splits inside the tile (S = 2 .. TI) as a chain of uniform branches.
+template <typename T, int TI, int S>
+__device__ __forceinline__ void sweep_mid_chain(const SweepArgs<T>& a, int it, int kci, double* smem, int j, int B,
+                                                int s)
 {
-    if (tile_is_fast(it, TI, a.nvx)) sweep_fast_dispatch<T, TI>(a, it, kci, smem, j, B);
-    else sweep_body<T, TI, true>(a, it, kci, smem, j, B);
+    if constexpr (S == TI) {
+        sweep_fast<T, TI, S>(a, it, kci, smem, j, B);
+    } else {
+        if (s == S) sweep_fast<T, TI, S>(a, it, kci, smem, j, B);
+        else sweep_mid_chain<T, TI, S + 1>(a, it, kci, smem, j, B, s);
+    }
+}
+
+// Tiles outside the edge-split set: the fast body compiled for their split
+// (full tiles of 4 or 8 rows split inside the tile) or for a ragged last
+// tile whose rows all have v_x > 0; any other tile takes the generic body.
+template <typename T, int TI>
+__device__ __forceinline__ void sweep_rest(const SweepArgs<T>& a, int it, int kci, double* smem, int j, int B)
+{
+    if constexpr (TI == 4 || TI == 8) {
+        if (tile_is_special(it, TI, a.nvx)) {
+            if ((it + 1) * TI > a.nvx) sweep_fast<T, TI, 0, true>(a, it, kci, smem, j, B);
+            else sweep_mid_chain<T, TI, 2>(a, it, kci, smem, j, B, tile_split(it, TI, a.nvx));
+            return;
+        }
+    }
+    sweep_body<T, TI, true>(a, it, kci, smem, j, B);
 }
 
 // Tiles of a launch: blockIdx -> (x chunk, entry of the launch's v_x tile
@@ -266,7 +313,7 @@ __global__ void __launch_bounds__(MAXB) k_sweep_generic(SweepArgs<T> a)
     extern __shared__ double smem[];
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
     const int it = a.tile_list[wg % a.n_list];
-    sweep_body<T, TI, true>(a, it, wg / a.n_list, smem, threadIdx.x, blockDim.x);
+    sweep_rest<T, TI>(a, it, wg / a.n_list, smem, threadIdx.x, blockDim.x);
 }
 
 // A sub-tile slot of a batched workgroup with no tile: take part in the same

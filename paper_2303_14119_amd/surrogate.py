@@ -229,7 +229,7 @@ def warm_start(solver, cfg, surrogate):
     return profile
 
 
-def time_to_saturation(solver, window_s=50e-12, rtol=1e-3, t_max=5e-9, check_steps=500):
+def time_to_saturation(solver, window_s=50e-12, rtol=1e-3, t_max=5e-9, check_steps=500, log=None, log_every=20000):
     """Step until the Section 2 test holds; returns (saturated, steps, wall s)."""
     import torch
     torch.cuda.synchronize()
@@ -238,6 +238,10 @@ def time_to_saturation(solver, window_s=50e-12, rtol=1e-3, t_max=5e-9, check_ste
     while True:
         solver.step(check_steps)
         steps += check_steps
+        if log and steps % log_every == 0:
+            st = solver.state()
+            log(f"  step {steps}: t {steps * solver.dt:.3e} s, sigma {st['sigma'] + st['sigma_lo']:.4e}, "
+                f"Gamma_see/Gamma_pe {st['g_see'] / max(st['g_pe'], 1e-300):.5f}, {time.perf_counter() - t0:.1f} s")
         if solver.saturated(window_s, rtol):
             torch.cuda.synchronize()
             return True, steps, time.perf_counter() - t0
@@ -314,7 +318,8 @@ def warmcold_cli(args, stream):
                 setup = time.perf_counter() - t0
             else:
                 setup = 0.0
-            sat, steps, wall = time_to_saturation(s, t_max=args.t_max, check_steps=args.check_steps)
+            sat, steps, wall = time_to_saturation(s, t_max=args.t_max, check_steps=args.check_steps,
+                                                  log=lambda m: print(m, flush=True))
             st = s.state()
             profiles[mode] = s.profile(NPTS)
             res[mode] = {"saturated": sat, "steps": steps, "sim_time_s": steps * s.dt, "wall_s": wall,
