@@ -99,8 +99,7 @@ struct Buffers {
     double* part_wall;// [n_it][2]
     double* part_top; // [n_it]
     double* part_lv;  // [nwg]
-    double* plane_sum;// [nx]   plane sums reduced over the v_x tiles
-    double* wall_sum; // [4]    wall primary, wall secondary, top, velocity-box outflow
+    double* plane_sum;// [nx]   plane sums reduced over the v_x tiles (single contexts)
     double* ne;       // [nx]
     double* ex;       // [nx]
     double* dxk;      // [nx], v_x Courant number of each plane

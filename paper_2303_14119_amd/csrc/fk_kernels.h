@@ -94,19 +94,6 @@ struct SweepArgs {
     int n_list;
 };
 
-// Reduction of the tile partials over the v_x tiles, fixed order: one
-// thread per x plane (coalesced over consecutive planes); workgroup 0 also
-// reduces the wall, top and velocity-box partials.
-struct ReduceArgs {
-    const double* __restrict__ part_n;      // [n_it][nx]
-    const double* __restrict__ part_wall;   // [n_it][2]
-    const double* __restrict__ part_top;    // [n_it]
-    const double* __restrict__ part_lv;     // [nwg]
-    double* __restrict__ plane_sum;         // [nx]
-    double* __restrict__ wall_sum;          // [4]: primary, secondary, top, velocity-box outflow
-    int nx, n_it, nwg;
-};
-
 // Buffer-resource access (CDNA raw buffer instructions).  A descriptor
 // covers one x plane; the row offset is a scalar, the column a 32-bit lane
 // offset.  Accesses at or beyond the descriptor's byte range read 0 and
@@ -437,49 +424,35 @@ __device__ __forceinline__ void moments_tile(const SweepArgs<T>& a, int wg, doub
     }
 }
 
-__device__ __forceinline__ void reduce_tiles(const ReduceArgs& a, double* sh)
+// Plane sums over the v_x tiles, one thread per x plane (coalesced over
+// consecutive planes), tiles added in order: the same sums the field
+// workgroup forms itself when it is given no plane_sum.
+__device__ __forceinline__ void plane_sums(const double* __restrict__ part_n, int nx, int n_it,
+                                           double* __restrict__ plane_sum)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < a.nx) {
-        double s = 0.0;
+    if (k >= nx) return;
+    double s = 0.0;
 #pragma unroll 16
-        for (int u = 0; u < a.n_it; ++u) s += a.part_n[(size_t)u * a.nx + k];
-        a.plane_sum[k] = s;
-    }
-    if (blockIdx.x != 0) return;
-    const int t = threadIdx.x;
-    double pe = 0.0, see = 0.0, top = 0.0, lv = 0.0;
-    for (int u = t; u < a.n_it; u += blockDim.x) {
-        pe += a.part_wall[2 * u];
-        see += a.part_wall[2 * u + 1];
-        top += a.part_top[u];
-    }
-#pragma unroll 4
-    for (int w = t; w < a.nwg; w += blockDim.x) lv += a.part_lv[w];
-    pe = block_sum(pe, sh);
-    see = block_sum(see, sh);
-    top = block_sum(top, sh);
-    lv = block_sum(lv, sh);
-    if (t == 0) {
-        a.wall_sum[0] = pe;
-        a.wall_sum[1] = see;
-        a.wall_sum[2] = top;
-        a.wall_sum[3] = lv;
-    }
+    for (int u = 0; u < n_it; ++u) s += part_n[(size_t)u * nx + k];
+    plane_sum[k] = s;
 }
 
 // ---------------------------------------------------------------- field
 
 struct FieldArgs {
-    const double* __restrict__ plane_sum;   // [nx]
-    const double* __restrict__ wall_sum;    // [4]
+    const double* __restrict__ plane_sum;   // [nx] plane sums already reduced over the tiles, or null
+    const double* __restrict__ part_n;      // [n_it][nx] plane sums of the v_x tiles
+    const double* __restrict__ part_wall;   // [n_it][2]  wall primary, wall secondary
+    const double* __restrict__ part_top;    // [n_it]     flux through x = L
+    const double* __restrict__ part_lv;     // [nwg]      velocity-box outflow
     const double* __restrict__ consts;  // zsum, srcnorm, injected per step, Eq 15 prefactor
     double* __restrict__ ne;
     double* __restrict__ ex;
     double* __restrict__ dxk;
     DevState* __restrict__ st;
     fk_state* __restrict__ ring;
-    int nx, advance;
+    int nx, n_it, nwg, advance;
     uint32_t mask;
     int emission_norm, trace_stride, trace_cap;
     double dx, dv2, dt, dvx, ex_ext;
@@ -497,9 +470,12 @@ __device__ __forceinline__ double wave_scan(double v)
     return v;
 }
 
-// Reduction of the moment partials of the new f, the 1D field solve and the
-// wall bookkeeping; one workgroup of kFieldThreads threads.  sh holds
-// 2 * kFieldThreads doubles.
+// Reduction of the moment partials of the new f over the v_x tiles (fixed
+// order), the 1D field solve and the wall bookkeeping; one workgroup of
+// kFieldThreads threads.  Thread t owns a contiguous segment of x planes and
+// keeps their densities in registers.  sh holds 2 * kFieldThreads doubles.
+constexpr int kFieldSegMax = 8;
+
 __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
 {
     const int t = threadIdx.x;
@@ -507,21 +483,54 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
     const int lane = t & 63, wave = t >> 6, nw = T >> 6;
     const int seg = (a.nx + T - 1) / T;
     const int kb = min(t * seg, a.nx), ke = min(kb + seg, a.nx);
+    const DevState old = *a.st;     // issued early: needed after the scans
 
-    // electron density per plane (the sweep has reduced the v_x tiles)
+    // electron density per plane: sum over the v_x tiles in tile order
+    double nloc[kFieldSegMax];
     double local = 0.0;
-    for (int k = kb; k < ke; ++k) {
-        const double nk = a.plane_sum[k] * a.dv2;
-        a.ne[k] = nk;
-        local += nk;
+    if (seg <= kFieldSegMax) {
+#pragma unroll
+        for (int q = 0; q < kFieldSegMax; ++q) nloc[q] = 0.0;
+        if (a.plane_sum) {
+#pragma unroll
+            for (int q = 0; q < kFieldSegMax; ++q)
+                if (kb + q < ke) nloc[q] = a.plane_sum[kb + q];
+        } else {
+#pragma unroll 4
+        for (int u = 0; u < a.n_it; ++u) {
+            const double* row = a.part_n + (size_t)u * a.nx;
+#pragma unroll
+            for (int q = 0; q < kFieldSegMax; ++q)
+                if (kb + q < ke) nloc[q] += row[kb + q];
+        }
+        }
+#pragma unroll
+        for (int q = 0; q < kFieldSegMax; ++q)
+            if (kb + q < ke) {
+                nloc[q] *= a.dv2;
+                a.ne[kb + q] = nloc[q];
+                local += nloc[q];
+            }
+    } else {
+        for (int k = kb; k < ke; ++k) {
+            double sk = 0.0;
+            if (a.plane_sum) sk = a.plane_sum[k];
+            else
+                for (int u = 0; u < a.n_it; ++u) sk += a.part_n[(size_t)u * a.nx + k];
+            a.ne[k] = sk * a.dv2;
+            local += sk * a.dv2;
+        }
     }
+    // wall, top and velocity-box partials: strided per thread, then over the
+    // waves in order
     double pe = 0.0, see = 0.0, top = 0.0, lv = 0.0;
-    if (t == 0) {
-        pe = a.wall_sum[0];
-        see = a.wall_sum[1];
-        top = a.wall_sum[2];
-        lv = a.advance ? a.wall_sum[3] : 0.0;
+    for (int u = t; u < a.n_it; u += T) {
+        pe += a.part_wall[2 * u];
+        see += a.part_wall[2 * u + 1];
+        top += a.part_top[u];
     }
+    if (a.advance)
+        for (int w = t; w < a.nwg; w += T) lv += a.part_lv[w];
 
     // exclusive prefix of the segment sums over the workgroup: wave scans,
     // then a scan of the wave totals
@@ -549,7 +558,6 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
     }
     const double below0 = wave_below + excl;
 
-    const DevState old = *a.st;
     double sig = old.sigma, sig_lo = old.sigma_lo;
     if (a.advance) {
         // Eq 18 with the fluxes of f^n, Neumaier-compensated across steps
@@ -563,8 +571,7 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
 
     // E_x at the cell centres: sigma / 2 eps0 minus the electron charge below
     double run = below0, cmax = 0.0;
-    for (int k = kb; k < ke; ++k) {
-        const double nk = a.ne[k];
+    auto field_at = [&](int k, double nk) {
         double e = (a.mask & FK_PHYS_SELF_FIELD)
                        ? sigma_now / (2.0 * kEps0) - kE / kEps0 * a.dx * (run + 0.5 * nk)
                        : 0.0;
@@ -574,6 +581,13 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
         a.dxk[k] = d;
         cmax = fmax(cmax, fabs(d));
         run += nk;
+    };
+    if (seg <= kFieldSegMax) {
+#pragma unroll
+        for (int q = 0; q < kFieldSegMax; ++q)
+            if (kb + q < ke) field_at(kb + q, nloc[q]);
+    } else {
+        for (int k = kb; k < ke; ++k) field_at(k, a.ne[k]);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) cmax = fmax(cmax, __shfl_xor(cmax, o, 64));

@@ -119,10 +119,10 @@ __global__ void __launch_bounds__(1024) k_moments(SweepArgs<T> a)
     moments_tile<T, TI>(a, blockIdx.x, smem);
 }
 
-__global__ void __launch_bounds__(256) k_reduce(ReduceArgs a)
+__global__ void __launch_bounds__(64) k_plane_sums(const double* __restrict__ part_n, int nx, int n_it,
+                                                    double* __restrict__ plane_sum)
 {
-    __shared__ double sh[256];
-    reduce_tiles(a, sh);
+    plane_sums(part_n, nx, n_it, plane_sum);
 }
 
 __global__ void __launch_bounds__(kFieldThreads) k_field(FieldArgs a)
@@ -333,8 +333,12 @@ void launch_moments(const fk_ctx* c, hipStream_t s)
 FieldArgs field_args(const fk_ctx* c, int advance)
 {
     FieldArgs a{};
-    a.plane_sum = c->b.plane_sum;
-    a.wall_sum = c->b.wall_sum;
+    a.part_n = c->b.part_n;
+    a.part_wall = c->b.part_wall;
+    a.part_top = c->b.part_top;
+    a.part_lv = c->b.part_lv;
+    a.n_it = c->L.n_it;
+    a.nwg = c->L.nwg;
     a.consts = c->b.consts;
     a.ne = c->b.ne;
     a.ex = c->b.ex;
@@ -357,18 +361,13 @@ FieldArgs field_args(const fk_ctx* c, int advance)
 
 void launch_field(const fk_ctx* c, int advance, hipStream_t s)
 {
-    ReduceArgs r{};
-    r.part_n = c->b.part_n;
-    r.part_wall = c->b.part_wall;
-    r.part_top = c->b.part_top;
-    r.part_lv = c->b.part_lv;
-    r.plane_sum = c->b.plane_sum;
-    r.wall_sum = c->b.wall_sum;
-    r.nx = c->p.nx;
-    r.n_it = c->L.n_it;
-    r.nwg = c->L.nwg;
-    hipLaunchKernelGGL(k_reduce, dim3((c->p.nx + 255) / 256), dim3(256), 0, s, r);
-    hipLaunchKernelGGL(k_field, dim3(1), dim3(kFieldThreads), 0, s, field_args(c, advance));
+    // many narrow workgroups for the plane sums (the bulk of the reduction),
+    // then the one-workgroup field solve on them
+    hipLaunchKernelGGL(k_plane_sums, dim3((c->p.nx + 63) / 64), dim3(64), 0, s, c->b.part_n, c->p.nx, c->L.n_it,
+                       c->b.plane_sum);
+    FieldArgs a = field_args(c, advance);
+    a.plane_sum = c->b.plane_sum;
+    hipLaunchKernelGGL(k_field, dim3(1), dim3(kFieldThreads), 0, s, a);
 }
 
 // one step from buffer `from` into the other
@@ -407,8 +406,7 @@ int alloc_buffers(fk_ctx* c, void* fa, void* fb)
                  o_pt = take((size_t)L.n_it_cap * 8), o_plv = take((size_t)L.nwg_cap * 8),
                  o_ne = take(p.nx * 8), o_ex = take(p.nx * 8), o_dxk = take(p.nx * 8),
                  o_consts = take(64), o_tiles = take((size_t)L.n_it_cap * sizeof(int)),
-                 o_psum = take((size_t)p.nx * 8), o_wsum = take(4 * 8),
-                 o_st = take(sizeof(DevState)),
+                 o_psum = take((size_t)p.nx * 8), o_st = take(sizeof(DevState)),
                  o_ring = take((size_t)p.trace_cap * sizeof(fk_state));
     if (hipMalloc(&c->pool, off) != hipSuccess) {
         c->pool = nullptr;
@@ -431,7 +429,6 @@ int alloc_buffers(fk_ctx* c, void* fa, void* fb)
     c->b.consts = (double*)(base + o_consts);
     c->b.tiles = (int*)(base + o_tiles);
     c->b.plane_sum = (double*)(base + o_psum);
-    c->b.wall_sum = (double*)(base + o_wsum);
     c->b.st = (DevState*)(base + o_st);
     c->b.ring = (fk_state*)(base + o_ring);
     FK_HIP(c, hipMemsetAsync(c->pool, 0, off, c->stream));
@@ -983,9 +980,9 @@ extern "C" int fk_autotune(fk_ctx* c, int trial_steps, fk_info* chosen)
 // compiled for one body and keeps its own register budget.  Workgroups pull
 // (instance, x chunk, up to 256 / block v_x tiles) work items from an
 // atomic counter, largest first, and run the item's tiles side by side.
-// The reductions and field solves of all instances follow as one launch
-// each; the three or four launches of a step are replayed from captured
-// HIP graphs.
+// One more launch reduces every instance's moments and solves its field
+// (a workgroup per instance); the launches of a step are replayed from
+// captured HIP graphs.
 
 namespace fk {
 
@@ -1000,7 +997,6 @@ __host__ __device__ constexpr int class_threads(int k) { return (k & 1) ? 192 : 
 
 struct BatchInst {
     SweepArgs<float> sw[2];   // from buffer 0 / from buffer 1
-    ReduceArgs rd;
     FieldArgs fd;
     int block, group, kc, nx, lds_doubles;
 };
@@ -1050,12 +1046,6 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_sweep(const BatchInst* 
     }
 }
 
-__global__ void __launch_bounds__(256) k_batch_reduce(const BatchInst* __restrict__ insts)
-{
-    __shared__ double sh[256];
-    reduce_tiles(insts[blockIdx.y].rd, sh);
-}
-
 // counters[0 .. kBatchClasses-1]: the sweep launches' work counters, cleared
 // for the next step once the sweeps of this one have finished
 __global__ void __launch_bounds__(kFieldThreads) k_batch_field(const BatchInst* __restrict__ insts, int* counters,
@@ -1081,7 +1071,6 @@ struct fk_batch {
     int n_active = 0;
     int grid = 0;
     size_t lds = 0;
-    int max_blocks_x = 1;
     std::vector<BatchInst> inst_host;
     std::vector<BatchItem> items_host;   // the classes' items, one range each
     int cls_off[kBatchClasses] = {0}, cls_n[kBatchClasses] = {0}, cls_grid[kBatchClasses] = {0};
@@ -1134,7 +1123,6 @@ void batch_launch_step(const fk_batch* b, int from, hipStream_t s)
 {
     if (b->ti == 4) batch_launch_sweeps<4>(b, from, s);
     else batch_launch_sweeps<8>(b, from, s);
-    hipLaunchKernelGGL(k_batch_reduce, dim3(b->max_blocks_x, b->n_active), dim3(256), 0, s, b->d_inst);
     hipLaunchKernelGGL(k_batch_field, dim3(b->n_active), dim3(kFieldThreads), 0, s, b->d_inst, b->d_counter, 1);
 }
 
@@ -1160,7 +1148,6 @@ int batch_build(fk_batch* b, int wgs_per_cu)
     b->items_host.clear();
     for (int k = 0; k < kBatchClasses; ++k) b->cls_off[k] = b->cls_n[k] = b->cls_grid[k] = 0;
     b->lds = 0;
-    b->max_blocks_x = 1;
     b->occ = wgs_per_cu;
     if (b->active.size() != b->inst.size()) b->active.assign(b->inst.size(), 1);
     std::vector<int> compact;
@@ -1174,15 +1161,6 @@ int batch_build(fk_batch* b, int wgs_per_cu)
         BatchInst d{};
         d.sw[0] = sweep_args<float>(c, 0);
         d.sw[1] = sweep_args<float>(c, 1);
-        d.rd.part_n = c->b.part_n;
-        d.rd.part_wall = c->b.part_wall;
-        d.rd.part_top = c->b.part_top;
-        d.rd.part_lv = c->b.part_lv;
-        d.rd.plane_sum = c->b.plane_sum;
-        d.rd.wall_sum = c->b.wall_sum;
-        d.rd.nx = c->p.nx;
-        d.rd.n_it = c->L.n_it;
-        d.rd.nwg = c->L.nwg;
         d.fd = field_args(c, 1);
         d.block = c->L.block;
         d.group = std::min(kBatchMaxGroup, kBatchThreads / c->L.block);
@@ -1190,7 +1168,6 @@ int batch_build(fk_batch* b, int wgs_per_cu)
         d.nx = c->p.nx;
         d.lds_doubles = (int)batch_slice_doubles(b->ti, c->L.block, c->L.kc);
         b->lds = std::max(b->lds, (size_t)d.group * d.lds_doubles * 8);
-        b->max_blocks_x = std::max(b->max_blocks_x, (c->p.nx + 255) / 256);
         b->inst_host.push_back(d);
         // tiles by body, in groups of d.group for every x chunk
         std::vector<int> tf, tg;
