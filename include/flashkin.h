@@ -235,26 +235,34 @@ int fk_autotune(fk_ctx* ctx, int trial_steps, fk_info* chosen);
 
 /* ---- batched instances ---------------------------------------------------
  * n independent runs of uneven sizes (the parameter sweep that feeds the
- * surrogate) advanced together: one persistent sweep launch per step takes
- * (instance, x chunk, v_x tiles) work items largest first, followed by one
- * reduction and one field launch for all instances; steps are replayed from
- * HIP graphs.  Every instance is FK_F32 with nvy <= 256.  Each instance
- * starts at f = 0, sigma = 0.  If autotune != 0 the tiling and the
- * persistent grid size are chosen by timing short trial runs first (the
- * instances are reset to f = 0 afterwards). */
+ * surrogate) advanced together; a project addition beyond the paper, whose
+ * runs each follow Section 2.  Persistent sweep launches take (instance,
+ * x chunk, v_x tiles) work items largest first from an atomic counter; one
+ * field launch then reduces and solves every instance (a workgroup each);
+ * steps are replayed from HIP graphs.  Every instance is FK_F32 with
+ * nvy <= 256 and starts at f = 0, sigma = 0.
+ *   mode 0: split launches (default): up to four sweep launches per step,
+ *           by tile body and workgroup width, each with its own register
+ *           budget;
+ *   mode 1: autotune: time short trial runs of tilings, grid sizes, item
+ *           schedules and both launch modes, keep the fastest, then reset
+ *           the instances to f = 0;
+ *   mode 2: one sweep launch per step for all instances and tiles.
+ * Results are bitwise the same in every mode and equal to single contexts
+ * with the same tiling. */
 typedef struct {
     int32_t n;             /* instances */
     int32_t tile_rows;     /* v_x rows per tile */
     int32_t tile_planes;   /* x planes per tile of instance 0 */
-    int32_t grid;          /* workgroups of the persistent launch */
+    int32_t grid;          /* workgroups of the largest persistent sweep launch */
     int32_t items;         /* work items per step */
     int64_t lds_bytes;     /* LDS per workgroup */
     int64_t cells;         /* sum of nx * nvx * nvy over the instances */
     int32_t schedule;      /* 0: items from an atomic counter, 1: static round-robin */
-    int32_t reserved;
+    int32_t sweep_launches;/* sweep launches per step (1 in mode 2) */
 } fk_batch_info_t;
 
-int fk_batch_create(const fk_params* params, int n, void* stream, int autotune, fk_batch** out);
+int fk_batch_create(const fk_params* params, int n, void* stream, int mode, fk_batch** out);
 int fk_batch_destroy(fk_batch* batch);
 
 /* Queue nsteps steps of every instance (asynchronous). */

@@ -988,12 +988,15 @@ namespace fk {
 
 constexpr int kBatchThreads = 256;
 constexpr int kBatchMaxGroup = kBatchThreads / 64;
-// Work classes, one sweep launch each: fast or generic body, workgroups of
-// 256 threads (v_y blocks of 64, 128 or 256 lanes: 4, 2 or 1 tiles side by
-// side) or of 192 threads (one tile of a 192-lane block, no idle wave).
-constexpr int kBatchClasses = 4;
-__host__ __device__ constexpr bool class_fast(int k) { return k < 2; }
-__host__ __device__ constexpr int class_threads(int k) { return (k & 1) ? 192 : 256; }
+// Work classes, one sweep launch each.  Split mode (the default) uses four:
+// main-body or other tiles, workgroups of 256 threads (v_y blocks of 64,
+// 128 or 256 lanes: 4, 2 or 1 tiles side by side) or of 192 threads (one
+// tile of a 192-lane block, no idle wave).  Single mode puts every tile in
+// class 4: one launch per step, each tile taking its body at run time.
+constexpr int kBatchClasses = 5;
+enum BatchBody { BODY_FAST = 0, BODY_REST = 1, BODY_ANY = 2 };
+__host__ __device__ constexpr int class_body(int k) { return k < 2 ? BODY_FAST : (k < 4 ? BODY_REST : BODY_ANY); }
+__host__ __device__ constexpr int class_threads(int k) { return (k == 1 || k == 3) ? 192 : 256; }
 
 struct BatchInst {
     SweepArgs<float> sw[2];   // from buffer 0 / from buffer 1
@@ -1008,7 +1011,7 @@ struct BatchItem {
 
 // sched 0: items taken from an atomic counter (dynamic); sched 1: workgroup
 // w takes items w, w + grid, ... of the cost-sorted list (static).
-template <int TI, bool FAST>
+template <int TI, int BODY>
 __global__ void __launch_bounds__(kBatchThreads) k_batch_sweep(const BatchInst* __restrict__ insts,
                                                                const BatchItem* __restrict__ items,
                                                                int n_items, int* __restrict__ counter, int from,
@@ -1038,8 +1041,11 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_sweep(const BatchInst* 
         if (sub < __builtin_amdgcn_readfirstlane(item.ntiles)) {
             const int it = __builtin_amdgcn_readfirstlane(item.tile[sub]);
             double* slot = smem + (size_t)sub * in->lds_doubles;
-            if (FAST) sweep_fast_dispatch<float, TI>(in->sw[from], it, kci, slot, j, B);
-            else sweep_rest<float, TI>(in->sw[from], it, kci, slot, j, B);
+            const SweepArgs<float>& a = in->sw[from];
+            if (BODY == BODY_FAST || (BODY == BODY_ANY && tile_is_fast(it, TI, a.nvx)))
+                sweep_fast_dispatch<float, TI>(a, it, kci, slot, j, B);
+            else
+                sweep_rest<float, TI>(a, it, kci, slot, j, B);
         } else {
             sweep_idle(np);
         }
@@ -1066,6 +1072,7 @@ struct fk_batch {
     hipStream_t cap_stream = nullptr;
     int ti = 8;
     int sched = 0;                // 0 dynamic (atomic counter), 1 static round-robin
+    int single = 0;               // 1: one sweep launch per step (class 4 only)
     int occ = 0;                  // workgroups per compute unit (0 = occupancy limit)
     std::vector<char> active;     // instances still stepped
     int n_active = 0;
@@ -1110,12 +1117,22 @@ void batch_launch_sweeps(const fk_batch* b, int from, hipStream_t s)
     for (int k = 0; k < kBatchClasses; ++k) {
         if (b->cls_n[k] == 0) continue;
         const BatchItem* items = b->d_items + b->cls_off[k];
-        if (class_fast(k))
-            hipLaunchKernelGGL((k_batch_sweep<TI, true>), dim3(b->cls_grid[k]), dim3(class_threads(k)), b->lds, s,
-                               b->d_inst, items, b->cls_n[k], b->d_counter + k, from, b->sched);
-        else
-            hipLaunchKernelGGL((k_batch_sweep<TI, false>), dim3(b->cls_grid[k]), dim3(class_threads(k)), b->lds, s,
-                               b->d_inst, items, b->cls_n[k], b->d_counter + k, from, b->sched);
+        const dim3 grid(b->cls_grid[k]), block(class_threads(k));
+        int* ctr = b->d_counter + k;
+        switch (class_body(k)) {
+        case BODY_FAST:
+            hipLaunchKernelGGL((k_batch_sweep<TI, BODY_FAST>), grid, block, b->lds, s, b->d_inst, items, b->cls_n[k],
+                               ctr, from, b->sched);
+            break;
+        case BODY_REST:
+            hipLaunchKernelGGL((k_batch_sweep<TI, BODY_REST>), grid, block, b->lds, s, b->d_inst, items, b->cls_n[k],
+                               ctr, from, b->sched);
+            break;
+        default:
+            hipLaunchKernelGGL((k_batch_sweep<TI, BODY_ANY>), grid, block, b->lds, s, b->d_inst, items, b->cls_n[k],
+                               ctr, from, b->sched);
+            break;
+        }
     }
 }
 
@@ -1126,16 +1143,20 @@ void batch_launch_step(const fk_batch* b, int from, hipStream_t s)
     hipLaunchKernelGGL(k_batch_field, dim3(b->n_active), dim3(kFieldThreads), 0, s, b->d_inst, b->d_counter, 1);
 }
 
+template <int TI>
+hipError_t batch_occupancy_t(int k, size_t lds, int* occ)
+{
+    const int nt = class_threads(k);
+    switch (class_body(k)) {
+    case BODY_FAST: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_batch_sweep<TI, BODY_FAST>, nt, lds);
+    case BODY_REST: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_batch_sweep<TI, BODY_REST>, nt, lds);
+    default: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_batch_sweep<TI, BODY_ANY>, nt, lds);
+    }
+}
+
 int batch_occupancy(int ti, int k, size_t lds, int* occ)
 {
-    hipError_t e;
-    const int nt = class_threads(k);
-    if (ti == 4)
-        e = class_fast(k) ? hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_batch_sweep<4, true>, nt, lds)
-                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_batch_sweep<4, false>, nt, lds);
-    else
-        e = class_fast(k) ? hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_batch_sweep<8, true>, nt, lds)
-                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_batch_sweep<8, false>, nt, lds);
+    const hipError_t e = ti == 4 ? batch_occupancy_t<4>(k, lds, occ) : batch_occupancy_t<8>(k, lds, occ);
     return e == hipSuccess ? FK_OK : FK_E_HIP;
 }
 
@@ -1174,6 +1195,19 @@ int batch_build(fk_batch* b, int wgs_per_cu)
         for (int it = 0; it < c->L.n_it; ++it)
             (tile_is_fast(it, b->ti, c->p.nvx) ? tf : tg).push_back(it);
         const int narrow = d.group * d.block == 192 ? 1 : 0;   // 192-thread workgroups
+        if (b->single) {
+            // one class: consecutive tiles in groups of d.group, any body
+            for (int kci = 0; kci < c->L.n_kc; ++kci)
+                for (int g0 = 0; g0 < c->L.n_it; g0 += d.group) {
+                    BatchItem it{};
+                    it.inst = (int)q;
+                    it.kci = kci;
+                    it.ntiles = std::min(c->L.n_it - g0, d.group);
+                    for (int u = 0; u < it.ntiles; ++u) it.tile[u] = g0 + u;
+                    cls[4].push_back(it);
+                }
+            continue;
+        }
         for (int kci = 0; kci < c->L.n_kc; ++kci)
             for (int body = 0; body < 2; ++body) {
                 const std::vector<int>& t = body == 0 ? tf : tg;
@@ -1223,7 +1257,7 @@ int batch_build(fk_batch* b, int wgs_per_cu)
             return set_error(&b->err, FK_E_HIP, "hipOccupancyMaxActiveBlocksPerMultiprocessor failed");
         if (occ < 1) return set_error(&b->err, FK_E_INVALID, "batch tiles need more LDS than a compute unit has");
         // the fast classes carry the bulk: they take the tuned occupancy
-        const int per_cu = (class_fast(k) && wgs_per_cu > 0) ? std::min(wgs_per_cu, occ) : occ;
+        const int per_cu = (class_body(k) != BODY_REST && wgs_per_cu > 0) ? std::min(wgs_per_cu, occ) : occ;
         b->cls_grid[k] = std::max(1, std::min(cus * per_cu, b->cls_n[k]));
         b->grid = std::max(b->grid, b->cls_grid[k]);
     }
@@ -1297,7 +1331,7 @@ int batch_reset(fk_batch* b)
 
 }  // namespace
 
-extern "C" int fk_batch_create(const fk_params* params, int n, void* stream, int autotune, fk_batch** out)
+extern "C" int fk_batch_create(const fk_params* params, int n, void* stream, int mode, fk_batch** out)
 {
     if (!out || !params || n < 1) return set_error(nullptr, FK_E_INVALID, "bad arguments to fk_batch_create");
     *out = nullptr;
@@ -1312,6 +1346,11 @@ extern "C" int fk_batch_create(const fk_params* params, int n, void* stream, int
     fk_batch* b = new (std::nothrow) fk_batch();
     if (!b) return set_error(nullptr, FK_E_OOM, "host allocation failed");
     b->stream = static_cast<hipStream_t>(stream);
+    if (mode < 0 || mode > 2) {
+        delete b;
+        return set_error(nullptr, FK_E_INVALID, "batch mode must be 0, 1 or 2");
+    }
+    b->single = mode == 2 ? 1 : 0;
     int rc = FK_OK;
     hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) rc = bfail(b, e, "hipStreamCreateWithFlags");
@@ -1327,23 +1366,25 @@ extern "C" int fk_batch_create(const fk_params* params, int n, void* stream, int
         else b->inst.push_back(c);
     }
     if (!rc) rc = batch_build(b, 0);
-    if (!rc && autotune) {
+    if (!rc && mode == 1) {
         // search the tiling (rows, planes) and the persistent grid size on a
         // short run, then start the instances again from f = 0
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = FK_E_HIP;
-        int best_ti = 8, best_kc = 32, best_occ = 0, best_sched = 0;
+        int best_ti = 8, best_kc = 32, best_occ = 0, best_sched = 0, best_single = 0;
         float best_ms = 1e30f;
         const int tis[2] = {4, 8};
         const int kcs[3] = {16, 32, 64};
-        const int occs[5] = {2, 3, 4, 6, 0};
+        const int occs[4] = {2, 3, 4, 0};
         for (int ti : tis)
             for (int kc : kcs)
                 for (int occ : occs)
-                for (int sched = 0; sched < 2; ++sched) {
+                for (int sched = 0; sched < 2; ++sched)
+                for (int single = 0; single < 2; ++single) {
                     if (rc) break;
                     b->ti = ti;
                     b->sched = sched;
+                    b->single = single;
                     for (auto c : b->inst) {
                         const int kcc = std::min(kc, c->p.nx);
                         if (!rc) rc = retile(c, ti, kcc < 4 ? 0 : kcc);
@@ -1363,6 +1404,7 @@ extern "C" int fk_batch_create(const fk_params* params, int n, void* stream, int
                         best_kc = kc;
                         best_occ = occ;
                         best_sched = sched;
+                        best_single = single;
                     }
                 }
         if (e0) (void)hipEventDestroy(e0);
@@ -1370,6 +1412,7 @@ extern "C" int fk_batch_create(const fk_params* params, int n, void* stream, int
         if (!rc) {
             b->ti = best_ti;
             b->sched = best_sched;
+            b->single = best_single;
             for (auto c : b->inst) {
                 const int kcc = std::min(best_kc, c->p.nx);
                 if (!rc) rc = retile(c, best_ti, kcc < 4 ? 0 : kcc);
@@ -1442,6 +1485,9 @@ extern "C" int fk_batch_info(const fk_batch* b, fk_batch_info_t* out)
     out->cells = cells;
     out->tile_planes = b->inst.empty() ? 0 : b->inst[0]->L.kc;
     out->schedule = b->sched;
+    int launches = 0;
+    for (int k = 0; k < kBatchClasses; ++k) launches += b->cls_n[k] > 0;
+    out->sweep_launches = launches;
     return FK_OK;
 }
 

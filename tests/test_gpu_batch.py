@@ -70,13 +70,18 @@ def test_batch_members_match_oracle(fk, autotune):
             assert abs(s - orc["sigma"]) <= 1e-5 * abs(orc["sigma"]) + 1e-30, m
 
 
-def test_batch_is_bitwise_a_standalone_context(fk):
+@pytest.mark.parametrize("single", [False, True])
+def test_batch_is_bitwise_a_standalone_context(fk, single):
+    """Split launches and one sweep launch per step give the same bits as
+    single contexts with the same tiling."""
     cfgs = small_instances(9, 5)
-    with fk.Batch(cfgs, tile_planes=16) as b:
+    with fk.Batch(cfgs, tile_planes=16, single_launch=single) as b:
+        info = b.info()
+        assert (info["sweep_launches"] == 1) == single
         b.step(45)
         b.sync()
         outs = [(v.f(), v.state()) for v in b.views]
-        ti = b.info()["tile_rows"]
+        ti = info["tile_rows"]
     for c, (fb, sb) in zip(cfgs, outs):
         with fk.Solver(c, "f32", tile_rows=ti, tile_planes=min(16, c["nx"])) as s:
             s.step(45)
