@@ -171,3 +171,23 @@ def test_checkpoint_resume_bitwise(fk):
         st = b.state()
         for q in ("step", "sigma", "sigma_lo", "g_pe", "g_see", "n_total"):
             assert st[q] == st_end[q], q
+
+
+def test_profiled_steps_time_every_sweep_and_change_nothing(fk):
+    """With profiling on, every sweep launch is bracketed by HIP events
+    (direct launches) and the state is bitwise the same as without it."""
+    cfg = W.c0()
+    f0 = W.random_state((cfg["nx"], cfg["nvx"], cfg["nvy"]), seed=2, scale=1e3).astype(np.float32)
+    out = []
+    for prof in (False, True):
+        with fk.Solver(cfg, "f32") as s:
+            s.write_state(f0, 1e-6)
+            s.set_profiling(prof)
+            s.step(40)
+            s.sync()
+            if prof:
+                kt = s.kernel_times()
+                assert kt["sweep_n"] == 40 and kt["field_n"] == 39
+                assert kt["sweep_ms"] > 0 and kt["field_ms"] > 0
+            out.append(s.f())
+    assert np.array_equal(out[0], out[1])

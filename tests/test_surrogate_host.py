@@ -1,0 +1,59 @@
+"""Host-side helpers of the surrogate pipeline (no GPU): feature scaling,
+target encoding, the picosecond trace stride and the error measures."""
+import math
+
+import numpy as np
+import pytest
+
+S = pytest.importorskip("paper_2303_14119_amd.surrogate")
+from paper_2303_14119_amd import workloads as W  # noqa: E402
+
+EPS0 = 8.8541878128e-12
+
+
+def test_features_map_the_sweep_box_to_unit_cube():
+    lo = W.config(nx=8, nvx=8, nvy=8, length=0.5e-3, ey=-1e6, delta_max=1.5, a_max_ev=250.0, t_se_ev=1.0)
+    hi = W.config(nx=8, nvx=8, nvy=8, length=5e-3, ey=-10e6, delta_max=3.5, a_max_ev=600.0, t_se_ev=5.0)
+    f = S.features([lo, hi])
+    assert np.allclose(f[0], -1.0) and np.allclose(f[1], 1.0)
+    # |E_y| is used, whatever the sign convention of the field
+    mid = dict(lo, ey=+5.5e6)
+    assert S.features([mid])[0][0] == pytest.approx(0.0, abs=1e-6)
+
+
+def test_encode_decode_round_trip():
+    rng = np.random.default_rng(0)
+    ey = -6e6
+    prof = 2 * EPS0 * abs(ey) * rng.uniform(-0.5, 1.5, S.NPTS)
+    y = S.encode(prof, 3.2e24, 1.7e23, ey)
+    assert y.shape == (S.NPTS + 2,) and y.dtype == np.float32
+    back, gpe, gsee = S.decode(y, ey)
+    assert np.allclose(back, prof, rtol=1e-6, atol=1e-6 * np.abs(prof).max())
+    assert gpe == pytest.approx(3.2e24, rel=1e-5) and gsee == pytest.approx(1.7e23, rel=1e-5)
+    # profiles are in units of 2 eps0 |E_y| (the scale of Eq 20)
+    assert S.encode(np.full(S.NPTS, 2 * EPS0 * abs(ey)), 1e24, 1e24, ey)[0] == pytest.approx(1.0)
+
+
+def test_trace_stride_is_about_a_picosecond():
+    assert S.trace_stride(2.343e-14) == 43
+    assert S.trace_stride(5e-15) == 200
+    assert S.trace_stride(3e-12) == 1          # never zero
+
+
+def test_profile_errors_measure_relative_l2():
+    ey = -5e6
+    p = np.linspace(1e-5, 2e-5, S.NPTS)
+    yt = S.encode(p, 1e24, 2e24, ey)
+    yp = S.encode(1.1 * p, 1.2e24, 2e24, ey)
+    e = S.profile_errors(np.array([yp]), np.array([yt]), np.array([[ey]]))[0]
+    assert e[0] == pytest.approx(0.1, rel=1e-5)
+    assert e[1] == pytest.approx(0.2, rel=1e-4) and e[2] == pytest.approx(0.0, abs=1e-5)
+
+
+def test_init_params_layout_and_scale():
+    dims = [5, 64, 7]
+    p = S.init_params(dims, 3)
+    assert p.size == 5 * 64 + 64 + 64 * 7 + 7
+    w1 = p[:5 * 64].reshape(64, 5)
+    assert abs(w1.std() - 1 / math.sqrt(5)) < 0.1
+    assert np.all(p[5 * 64:5 * 64 + 64] == 0)
