@@ -57,15 +57,21 @@ __device__ __forceinline__ float gelu_grad(float z)
     return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
 }
 
-// One workgroup of 4 waves computes a 64 x 64 tile of C; each wave a 32 x 32
-// block with v_mfma_f32_32x32x16_bf16.  Lane l holds A[row l%32][k0 + 8(l/32)
+// One workgroup of 4 waves computes a 32 x 32 tile of C with
+// v_mfma_f32_32x32x16_bf16, splitting K: wave w takes the K steps
+// w, w + 4, w + 8, ... (16 each), so each wave's chain of dependent loads is
+// a quarter of K; the four partial tiles are summed through LDS (fixed
+// order) and wave 0 runs the epilogue.  Lane l holds A[row l%32][k0 + 8(l/32)
 // .. +7] and B[col l%32][same k] and accumulates C element e at row
-// 8(e/4) + 4(l/32) + e%4, column l%32 of the wave's block.
+// 8(e/4) + 4(l/32) + e%4, column l%32 of the tile.
+constexpr int kGemmTile = 32;
+
 __global__ void __launch_bounds__(256) k_gemm_nt(GemmArgs g)
 {
+    __shared__ float part[3][16][64];       // waves 1..3: [element][lane]
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int m0 = blockIdx.y * 64 + (w >> 1) * 32;
-    const int n0 = blockIdx.x * 64 + (w & 1) * 32;
+    const int m0 = blockIdx.y * kGemmTile;
+    const int n0 = blockIdx.x * kGemmTile;
     const int ra = m0 + (lane & 31), rb = n0 + (lane & 31);
     const int kk = 8 * (lane >> 5);
     const bool a_ok = ra < g.M, b_ok = rb < g.N;
@@ -74,11 +80,19 @@ __global__ void __launch_bounds__(256) k_gemm_nt(GemmArgs g)
     f32x16 acc = {0};
     const bf16x8 zero = {0};
 #pragma unroll 8
-    for (int k0 = 0; k0 < g.K; k0 += 16) {
+    for (int k0 = 16 * w; k0 < g.K; k0 += 64) {
         const bf16x8 a = a_ok ? *reinterpret_cast<const bf16x8*>(pa + k0) : zero;
         const bf16x8 b = b_ok ? *reinterpret_cast<const bf16x8*>(pb + k0) : zero;
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
     }
+    if (w > 0) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) part[w - 1][e][lane] = acc[e];
+    }
+    __syncthreads();
+    if (w > 0) return;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[e] = ((acc[e] + part[0][e][lane]) + part[1][e][lane]) + part[2][e][lane];
     const int col = n0 + (lane & 31);
     if (col >= g.N) return;
     const float bcol = (g.epi == EPI_HIDDEN || g.epi == EPI_OUTPUT) ? g.bias[col] : 0.0f;
@@ -276,7 +290,7 @@ int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
 void launch_gemm(const fk_mlp* n, const GemmArgs& g)
 {
-    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
+    dim3 grid((g.N + kGemmTile - 1) / kGemmTile, (g.M + kGemmTile - 1) / kGemmTile);
     hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, n->stream, g);
 }
 
