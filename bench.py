@@ -151,6 +151,9 @@ def main():
                     help="steps run before the warmup to drive the state into the avalanche")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (counter calibration)")
+    ap.add_argument("--workload", choices=("c1", "c4"), default="c1",
+                    help="c1: 2048x256x256 (the headline); c4: 4096x384x384 (no CPU baseline: one "
+                         "oracle step takes minutes there)")
     ap.add_argument("--mode", choices=("c1", "batch", "mlp"), default="c1",
                     help="c1: the headline line (default); batch: the 64-instance batched sweep; "
                          "mlp: surrogate training steps (both for profiling, one JSON line each)")
@@ -168,7 +171,7 @@ def main():
     from paper_2303_14119_amd import flashkin as fk
     from paper_2303_14119_amd import workloads as W
 
-    cfg = W.c1()
+    cfg = W.c1() if args.workload == "c1" else W.c4()
     dev = torch.device("cuda:0")
     torch.cuda.init()
     if args.calib_copy:
@@ -216,7 +219,7 @@ def main():
     field_ms = kt["field_ms"] / max(kt["field_n"], 1)
     bytes_per_launch = 8.0 * cells
     achieved = bytes_per_launch / (sweep_ms * 1e-3) / 1e9
-    traffic = measured_traffic()
+    traffic = measured_traffic() if args.workload == "c1" else None   # counters taken on c1
     out = {
         "metric": "Gcell-updates/s",
         "value": round(value, 3),
@@ -230,8 +233,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "plain single run, 2048x256x256 cells over 1 mm, |E_y| 8 MV/m, "
-                               "delta_max 2.2, A_max 350 eV, FP32 f, FP64 sigma and fluxes",
+        "config": {"workload": (f"plain single run, {cfg['nx']}x{cfg['nvx']}x{cfg['nvy']} cells over 1 mm, "
+                                f"|E_y| {abs(cfg['ey']) / 1e6:g} MV/m, delta_max {cfg['delta_max']:g}, "
+                                f"A_max {cfg['a_max_ev']:g} eV, FP32 f, FP64 sigma and fluxes"),
                    "nx": cfg["nx"], "nvx": cfg["nvx"], "nvy": cfg["nvy"], "cells": cells,
                    "dt_s": s.dt, "step_start": st["step"] - 2 * args.steps,
                    "sigma_at_end": st["sigma"] + st["sigma_lo"],
@@ -244,7 +248,7 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_per_launch},
         "cpu_baseline": None,
     }
-    if not args.no_cpu:
+    if not args.no_cpu and args.workload == "c1":
         out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out), flush=True)
 

@@ -94,7 +94,7 @@ typedef struct {
     int32_t trace_stride;    /* record observables every trace_stride steps (>= 1) */
     int32_t trace_cap;       /* records held on the device between drains (>= 1) */
     int32_t tile_rows;       /* v_x rows per tile, 0 = library choice */
-    int32_t tile_planes;     /* x planes per tile, 0 = library choice */
+    int32_t tile_planes;     /* x planes per tile; 0: chosen at creation so the sweep launch fills whole rounds of the device's workgroup slots (fk_validate reports a host-side estimate, fk_query the choice) */
 } fk_params;
 
 /* Observables of the state (f^n, sigma^n) after n steps.  The fluxes are

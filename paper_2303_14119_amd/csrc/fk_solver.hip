@@ -646,6 +646,60 @@ std::vector<std::pair<int, int>> tile_candidates(const fk_params& p)
     return out;
 }
 
+// Workgroups of a layout's main sweep kernel that fit on one compute unit.
+int sweep_wgs_per_cu(const Layout& L)
+{
+    int occ = 0;
+    hipError_t e;
+    const bool small = L.block <= 512;
+    if (L.elem == 4) {
+        if (L.ti == 16)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sweep<float, 16, 512>, L.block, L.lds_sweep);
+        else if (L.ti == 8)
+            e = small ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sweep<float, 8, 512>, L.block, L.lds_sweep)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sweep<float, 8, 1024>, L.block, L.lds_sweep);
+        else
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sweep<float, 4, 1024>, L.block, L.lds_sweep);
+    } else {
+        e = L.ti == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sweep<double, 8, 512>, L.block, L.lds_sweep)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sweep<double, 4, 1024>, L.block, L.lds_sweep);
+    }
+    return e == hipSuccess ? occ : 0;
+}
+
+// x planes per tile when the caller leaves it open: among 16 .. 128 (steps
+// of 8), the count whose workgroups fill the last round of the device's
+// workgroup slots best (compute units x workgroups per unit), the longest
+// on ties.  With one 6-wave workgroup per unit (384 v_y lanes, 16-row
+// tiles) a 4.03-round launch ran 14% slower than a whole number of rounds.
+void choose_planes(const fk_params* p, Layout* L)
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+        return;
+    double best = -1.0;
+    Layout pick = *L;
+    for (int kc = 16; kc <= 128 && kc <= std::max(16, p->nx); kc += 8) {
+        fk_params q = *p;
+        q.tile_rows = L->ti;
+        q.tile_planes = std::min(kc, p->nx);
+        Layout t;
+        if (derive_layout(&q, &t, nullptr) != FK_OK) continue;
+        const int occ = sweep_wgs_per_cu(t);
+        if (occ < 1) continue;
+        const double slots = (double)cus * occ;
+        const double rounds = std::ceil(t.nwg / slots);
+        const double fill = t.nwg / (rounds * slots);
+        if (fill >= best - 1e-9) {     // ties go to the longer x runs (later kc)
+            best = fill;
+            pick = t;
+        }
+    }
+    if (best > 0.0) *L = pick;
+    (void)hipGetLastError();
+}
+
 int create_impl(const fk_params* p, void* stream, void* fa, void* fb, fk_ctx** out, bool member = false)
 {
     if (!out) return set_error(nullptr, FK_E_INVALID, "out is NULL");
@@ -654,6 +708,7 @@ int create_impl(const fk_params* p, void* stream, void* fa, void* fb, fk_ctx** o
     std::string why;
     int rc = derive_layout(p, &L, &why);
     if (rc) return set_error(nullptr, rc, why);
+    if (p->tile_planes == 0) choose_planes(p, &L);
     if ((fa == nullptr) != (fb == nullptr)) return set_error(nullptr, FK_E_INVALID, "borrowed buffers: give both or neither");
     if (fa && fa == fb) return set_error(nullptr, FK_E_INVALID, "borrowed buffers must differ");
     fk_ctx* c = new (std::nothrow) fk_ctx();
