@@ -31,6 +31,32 @@ __device__ __forceinline__ int xcd_remap(int wg, int nwg)
 // signs that select wall, emission and source cells never depend on rounding.
 __device__ __forceinline__ double cell_v(int i, int n, double dv) { return (i + 0.5 - 0.5 * n) * dv; }
 
+// A double moved across lanes by a DPP control (two 32-bit halves); lanes
+// whose source is outside the row or whose row is masked off read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, ROWS, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, ROWS, 0xf, true);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the 64 lanes of a wavefront in the vector ALU (no LDS traffic),
+// fixed order: an inclusive scan inside each row of 16 lanes (shifts by 1,
+// 2, 4, 8), then row totals passed on by the row broadcasts; lane 63 holds
+// the total.
+__device__ __forceinline__ double wave_total(double v)
+{
+    v += dpp_move<0x111, 0xf>(v);   // row_shr:1
+    v += dpp_move<0x112, 0xf>(v);   // row_shr:2
+    v += dpp_move<0x114, 0xf>(v);   // row_shr:4
+    v += dpp_move<0x118, 0xf>(v);   // row_shr:8
+    v += dpp_move<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp_move<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
 // Sum over the 64 lanes of a wavefront; lane 0 holds a result that does not
 // depend on scheduling (fixed butterfly order).
 __device__ __forceinline__ double wave_sum(double v)
@@ -293,8 +319,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, int it, int kc
         double sn = 0.0;
 #pragma unroll
         for (int r = 0; r < TI; ++r) sn += (double)f3[r];
-        sn = wave_sum(sn);
-        if (lane == 0) wsum[(k - k0) * nw + wave] = sn;
+        sn = wave_total(sn);
+        if (lane == 63) wsum[(k - k0) * nw + wave] = sn;
         if (k == 0) {
 #pragma unroll
             for (int r = 0; r < TI; ++r) {
@@ -390,8 +416,8 @@ __device__ __forceinline__ void moments_tile(const SweepArgs<T>& a, int wg, doub
             }
             if (k == a.nx - 1 && v > 0.0) stop += v * fv;
         }
-        sn = wave_sum(sn);
-        if (lane == 0) wsum[(k - k0) * nw + wave] = sn;
+        sn = wave_total(sn);
+        if (lane == 63) wsum[(k - k0) * nw + wave] = sn;
     }
     __syncthreads();
     for (int kk = j; kk < k1 - k0; kk += blockDim.x) {

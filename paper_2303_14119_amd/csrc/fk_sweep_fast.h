@@ -196,8 +196,8 @@ __device__ __forceinline__ void sweep_fast(const SweepArgs<T>& a, int it, int kc
         double sn = 0.0;
 #pragma unroll
         for (int r = 0; r < TI; ++r) sn += (double)f3[r];
-        sn = wave_sum(jok ? sn : 0.0);
-        if (lane == 0) wsum[(k - k0) * nw + wave] = sn;
+        sn = wave_total(jok ? sn : 0.0);
+        if (lane == 63) wsum[(k - k0) * nw + wave] = sn;
         if (k == 0 && jok) {
 #pragma unroll
             for (int r = 1; r < (S < TI + 1 ? S : TI + 1); ++r) {   // output rows with v_x <= 0
