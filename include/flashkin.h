@@ -74,7 +74,9 @@ enum {
  * abi_version = FK_ABI_VERSION.  Inputs of Section 2's parameter list. */
 typedef struct {
     uint32_t struct_size, abi_version;
-    int32_t nx, nvx, nvy;    /* cells in x (normal to the surface), v_x, v_y; each >= 1, nvy <= 1024 */
+    int32_t nx, nvx, nvy;    /* cells in x (normal to the surface), v_x, v_y; each >= 1; nvy <= 1024 for
+                              * FK_F32 and <= 960 for FK_F64 (a tile's v_y exchange must fit in 64 KB of
+                              * LDS; larger values fail with FK_E_INVALID) */
     int32_t dtype;           /* FK_F32 or FK_F64 */
     double length_m;         /* domain extent normal to the surface (x in [0, L]) */
     double vmax_x, vmax_y;   /* velocity box [-vmax, vmax] in each direction, m/s */

@@ -67,6 +67,15 @@ def test_validate_rejects(kw, code):
     assert fk.fk_last_error(None)
 
 
+def test_width_limits_per_precision():
+    """nvy up to 1024 in FP32, up to 960 in FP64 (the tile's v_y exchange
+    must fit in 64 KB of LDS)."""
+    for nvy, dtype, code in ((1024, "f32", fk.OK), (960, "f64", fk.OK), (1024, "f64", fk.E_INVALID)):
+        cfg = W.config(nx=4, nvx=6, nvy=nvy, length=1e-5, ey=-4e6, delta_max=2.5, a_max_ev=400.0, cfl=0.8)
+        p = fk.make_params(cfg, dtype)
+        assert fk.fk_validate(C.byref(p), None) == code, (nvy, dtype)
+
+
 def test_struct_size_and_version_are_checked():
     p = fk.make_params(W.c0())
     p.struct_size -= 8

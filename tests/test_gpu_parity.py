@@ -108,6 +108,9 @@ RAGGED = [
     (5, 7, 3, W.ALL, -5e6, 0.0, 0),
     (1, 4, 1, W.ALL, -5e6, 0.0, 0),
     (64, 40, 257, W.VX | W.VY, -3e6, 2e6, 0),
+    # v_y blocks above 512 lanes (the 1024-thread kernels), up to the maximum
+    (5, 9, 700, W.ALL, -5e6, 0.0, 0),
+    (3, 6, 960, W.ALL & ~W.SRC, -4e6, 1e5, 0),
 ]
 
 
