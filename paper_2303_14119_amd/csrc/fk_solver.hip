@@ -1,8 +1,10 @@
 // fk_solver.hip -- one simulation context: tables, time step, state I/O.
 //
-// Kernels per step: the fused sweep over all tiles of f (HBM-bound), then
-// the one-workgroup field kernel that reduces the new moments and prepares
-// the next step.  Steps are replayed from captured HIP graphs.
+// Kernels per step: the fused sweep over all tiles of f (HBM-bound; a
+// second launch for the tiles outside the main body), the plane sums of
+// the tile partials, then the one-workgroup field kernel that reduces the
+// wall partials, updates sigma and prepares the next step.  Steps are
+// replayed from captured HIP graphs.
 #include <algorithm>
 #include <cmath>
 #include <cstring>

@@ -1,4 +1,4 @@
-"""Batched instances (one persistent sweep launch per step) and the tiling
+"""Batched instances (persistent sweep launches: split by work class, or one per step) and the tiling
 autotuner, on the GPU: every instance against the FP64 oracle, and bitwise
 against a standalone context with the same tiling."""
 import os
