@@ -102,3 +102,19 @@ def test_saturation_check():
     assert fk.saturation_check(rising, 50e-12, 1e-2)
     empty = [rec(i * 1e-12, 0.0, 0.0, 0.0) for i in range(200)]
     assert not fk.saturation_check(empty, 50e-12, 1e-3)              # nothing has arrived yet
+
+
+def test_batch_rejects_before_touching_the_gpu():
+    """Batched instances are FP32 with nvy <= 256 and the mode is 0, 1 or 2;
+    these are checked on the host before any device call."""
+    good = W.config(nx=16, nvx=16, nvy=64, length=1e-3, ey=-5e6, delta_max=2.5, a_max_ev=400.0)
+    wide = dict(good, nvy=300)
+    for cfgs, dtype in (([good], "f64"), ([good, wide], "f32")):
+        arr = (fk.fk_params * len(cfgs))(*[fk.make_params(c, dtype) for c in cfgs])
+        h = C.c_void_p()
+        assert fk.fk_batch_create(arr, len(cfgs), None, 0, C.byref(h)) == fk.E_INVALID
+        assert not h.value
+        assert fk.fk_batch_last_error(None)
+    arr = (fk.fk_params * 1)(fk.make_params(good, "f32"))
+    assert fk.fk_batch_create(arr, 0, None, 0, C.byref(C.c_void_p())) == fk.E_INVALID
+    assert fk.fk_batch_create(arr, 1, None, 3, C.byref(C.c_void_p())) == fk.E_INVALID
