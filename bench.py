@@ -147,6 +147,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--sample-every", type=int, default=4,
+                    help="HIP events around every n-th step's kernels in the timed region")
     ap.add_argument("--pre-steps", type=int, default=3000,
                     help="steps run before the warmup to drive the state into the avalanche")
     ap.add_argument("--calib-copy", action="store_true",
@@ -190,9 +192,10 @@ def main():
     s.sync()
     torch.cuda.synchronize()
 
-    # timed region: direct launches with a HIP event pair around every sweep
-    # launch on the library's stream (the live kernel timing)
-    s.set_profiling(True)
+    # timed region: direct launches; every sample_every-th step has HIP
+    # events on the library's stream around its sweep launch and its
+    # reduction and field kernels (the live kernel timing)
+    s.set_profiling(True, every=args.sample_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s.step(args.steps)
@@ -245,6 +248,7 @@ def main():
                      "traffic": traffic,
                      "kernel": "k_sweep (fused x/v_x/v_y upwind + source + moments)",
                      "kernel_ms": round(sweep_ms, 5), "reduce_field_interval_ms": round(field_ms, 5),
+                     "timed_launches": kt["sweep_n"], "sample_every": args.sample_every,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
         "cpu_baseline": None,
     }

@@ -218,13 +218,16 @@ int fk_saturated(fk_ctx* ctx, double window_s, double rtol, int* out);
 /* The same test on a caller-held trace (host only, no GPU). */
 int fk_saturation_check(const fk_state* trace, size_t n, double window_s, double rtol, int* out);
 
-/* Kernel timing.  While profiling is on, fk_step launches without graphs
- * and records a HIP event on the context's stream before and after every
- * sweep launch; fk_kernel_times synchronises and returns the summed
- * milliseconds and counts of the sweep launches and of the intervals from
- * one sweep's end to the next sweep's start (the reduction and field
- * kernels) since profiling was switched on. */
-int fk_set_profiling(fk_ctx* ctx, int on);
+/* Kernel timing.  fk_set_profiling(ctx, every) with every >= 1 switches
+ * profiling on: fk_step then launches every step directly (no graphs) and,
+ * for every `every`-th step counted from the call (the first included),
+ * records three HIP events on the context's stream: before and after the
+ * sweep launch and after the reduction and field kernels.  every = 0
+ * switches it off; every < 0 is FK_E_INVALID.  Each call drops the events
+ * taken so far.  fk_kernel_times synchronises and returns the summed
+ * milliseconds and counts of the sampled sweep launches and of their
+ * reduction-and-field intervals. */
+int fk_set_profiling(fk_ctx* ctx, int every);
 int fk_kernel_times(fk_ctx* ctx, double* sweep_ms, int64_t* sweep_count, double* field_ms,
                     int64_t* field_count);
 

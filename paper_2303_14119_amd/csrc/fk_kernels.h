@@ -57,13 +57,30 @@ __device__ __forceinline__ double wave_total(double v)
     return v;
 }
 
-// Sum over the 64 lanes of a wavefront; lane 0 holds a result that does not
-// depend on scheduling (fixed butterfly order).
-__device__ __forceinline__ double wave_sum(double v)
+// Value of lane 63, the same in every lane.
+__device__ __forceinline__ double lane63(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), 63);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Sum over the 64 lanes of a wavefront (the fixed order of wave_total), the
+// same in every lane.
+__device__ __forceinline__ double wave_sum(double v) { return lane63(wave_total(v)); }
+
+// Maximum over the 64 lanes of a wavefront of values >= 0, the same in every
+// lane (lanes shifted in from outside a row read 0, which no value is below).
+__device__ __forceinline__ double wave_max_nonneg(double v)
+{
+    v = fmax(v, dpp_move<0x111, 0xf>(v));
+    v = fmax(v, dpp_move<0x112, 0xf>(v));
+    v = fmax(v, dpp_move<0x114, 0xf>(v));
+    v = fmax(v, dpp_move<0x118, 0xf>(v));
+    v = fmax(v, dpp_move<0x142, 0xa>(v));
+    v = fmax(v, dpp_move<0x143, 0xc>(v));
+    return lane63(v);
 }
 
 // Fixed-order sum over a workgroup of blockDim.x (a power of two, <= 1024)
@@ -116,6 +133,7 @@ struct SweepArgs {
     double dvx, dt_dx;                  // v_x of row i is cell_v(i, nvx, dvx)
     double dy;                          // signed v_y Courant number
     int x_on;
+    int store_nt;                       // 1: stores of f^{n+1} are non-temporal (whole 128 B lines per row)
     const int* __restrict__ tile_list;  // v_x tile indices handled by this launch
     int n_list;
 };
@@ -135,24 +153,25 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint32_t bytes)
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, kRsrcWord3);
 }
 
-template <typename T> __device__ __forceinline__ T bload(rsrc_t r, int voff, int soff);
-template <> __device__ __forceinline__ float bload<float>(rsrc_t r, int voff, int soff)
+// Cache policy operand of the buffer instructions: bit 1 marks the access
+// non-temporal (streamed through L2 without being kept).
+constexpr int kCpDefault = 0, kCpStream = 2;
+
+template <typename T, int CP = kCpDefault> __device__ __forceinline__ T bload(rsrc_t r, int voff, int soff)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, CP));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, CP));
 }
-template <> __device__ __forceinline__ double bload<double>(rsrc_t r, int voff, int soff)
+template <typename T, int CP = kCpDefault> __device__ __forceinline__ void bstore(T v, rsrc_t r, int voff, int soff)
 {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
-}
-template <typename T> __device__ __forceinline__ void bstore(T v, rsrc_t r, int voff, int soff);
-template <> __device__ __forceinline__ void bstore<float>(float v, rsrc_t r, int voff, int soff)
-{
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), r, voff, soff, 0);
-}
-template <> __device__ __forceinline__ void bstore<double>(double v, rsrc_t r, int voff, int soff)
-{
-    typedef int v2i __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i, v), r, voff, soff, 0);
+    if constexpr (sizeof(T) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), r, voff, soff, CP);
+    } else {
+        typedef int v2i __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i, v), r, voff, soff, CP);
+    }
 }
 
 // One workgroup owns v_x rows [i0, i0+TI) for all v_y columns (one thread per
@@ -311,8 +330,13 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, int it, int kc
 
         {
             const rsrc_t po = plane_out(k);
+            if (a.store_nt) {
 #pragma unroll
-            for (int r = 0; r < TI; ++r) bstore<T>(f3[r], po, vo[r + 1], 0);
+                for (int r = 0; r < TI; ++r) bstore<T, kCpStream>(f3[r], po, vo[r + 1], 0);
+            } else {
+#pragma unroll
+                for (int r = 0; r < TI; ++r) bstore<T>(f3[r], po, vo[r + 1], 0);
+            }
         }
 
         // moments of f^{n+1}
@@ -458,9 +482,18 @@ __device__ __forceinline__ void plane_sums(const double* __restrict__ part_n, in
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nx) return;
+    // all loads of a chunk of tiles are issued before the first add, so a
+    // chunk costs one memory latency; the adds stay in tile order
+    constexpr int kChunk = 32;
     double s = 0.0;
-#pragma unroll 16
-    for (int u = 0; u < n_it; ++u) s += part_n[(size_t)u * nx + k];
+    for (int u0 = 0; u0 < n_it; u0 += kChunk) {
+        double v[kChunk];
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q) v[q] = u0 + q < n_it ? part_n[(size_t)(u0 + q) * nx + k] : 0.0;
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q)
+            if (u0 + q < n_it) s += v[q];
+    }
     plane_sum[k] = s;
 }
 
@@ -483,18 +516,6 @@ struct FieldArgs {
     int emission_norm, trace_stride, trace_cap;
     double dx, dv2, dt, dvx, ex_ext;
 };
-
-// Inclusive prefix sum over the 64 lanes of a wavefront (fixed order).
-__device__ __forceinline__ double wave_scan(double v)
-{
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const double u = __shfl_up(v, o, 64);
-        if (lane >= o) v += u;
-    }
-    return v;
-}
 
 // Reduction of the moment partials of the new f over the v_x tiles (fixed
 // order), the 1D field solve and the wall bookkeeping; one workgroup of
@@ -560,7 +581,7 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
 
     // exclusive prefix of the segment sums over the workgroup: wave scans,
     // then a scan of the wave totals
-    const double incl = wave_scan(local);
+    const double incl = wave_total(local);     // inclusive scan over the wave
     double excl = __shfl_up(incl, 1, 64);
     if (lane == 0) excl = 0.0;
     double* wtot = sh;              // [nw]
@@ -597,13 +618,13 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
 
     // E_x at the cell centres: sigma / 2 eps0 minus the electron charge below
     double run = below0, cmax = 0.0;
+    const double e_wall = sigma_now / (2.0 * kEps0), e_per_n = kE / kEps0 * a.dx;
+    const double d_per_e = (a.mask & FK_PHYS_VX) ? -kE / kMe * a.dt / a.dvx : 0.0;   // Courant number per V/m
     auto field_at = [&](int k, double nk) {
-        double e = (a.mask & FK_PHYS_SELF_FIELD)
-                       ? sigma_now / (2.0 * kEps0) - kE / kEps0 * a.dx * (run + 0.5 * nk)
-                       : 0.0;
+        double e = (a.mask & FK_PHYS_SELF_FIELD) ? e_wall - e_per_n * (run + 0.5 * nk) : 0.0;
         e += a.ex_ext;
         a.ex[k] = e;
-        const double d = (a.mask & FK_PHYS_VX) ? (-kE * e / kMe) * a.dt / a.dvx : 0.0;
+        const double d = d_per_e * e;
         a.dxk[k] = d;
         cmax = fmax(cmax, fabs(d));
         run += nk;
@@ -615,8 +636,7 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
     } else {
         for (int k = kb; k < ke; ++k) field_at(k, a.ne[k]);
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) cmax = fmax(cmax, __shfl_xor(cmax, o, 64));
+    cmax = wave_max_nonneg(cmax);
     if (lane == 0) red[wave * 5 + 4] = cmax;
     __syncthreads();
     if (t == 0) {
@@ -668,7 +688,15 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
             !isfinite(sigma_now))
             ns.flags |= kFlagNonfinite;
         *a.st = ns;
-        if (ns.step % a.trace_stride == 0) {
+        // trace slot: 32-bit arithmetic while the step count fits
+        int64_t rec = -1;
+        if (ns.step >= 0 && ns.step <= 0xffffffffLL) {
+            const unsigned st32 = (unsigned)ns.step, q = st32 / (unsigned)a.trace_stride;
+            if (q * (unsigned)a.trace_stride == st32) rec = q % (unsigned)a.trace_cap;
+        } else if (ns.step % a.trace_stride == 0) {
+            rec = (ns.step / a.trace_stride) % a.trace_cap;
+        }
+        if (rec >= 0) {
             fk_state r;
             r.step = ns.step;
             r.t = (double)ns.step * a.dt;
@@ -681,7 +709,7 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
             r.loss_v = loss_v;
             r.n_total = n_total;
             r.resid = resid;
-            a.ring[(ns.step / a.trace_stride) % a.trace_cap] = r;
+            a.ring[rec] = r;
         }
     }
 }

@@ -57,6 +57,15 @@ __device__ __forceinline__ float gelu_grad(float z)
     return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
 }
 
+// One launch runs one or two independent products (the weight and the input
+// gradient of a layer need only its dZ): workgroups [0, tiles0) take tiles
+// of p[0], the rest tiles of p[1]; ntn[i] is p[i]'s number of column tiles.
+struct GemmPair {
+    GemmArgs p[2];
+    int tiles0;
+    int ntn[2];
+};
+
 // One workgroup of 4 waves computes a 32 x 32 tile of C with
 // v_mfma_f32_32x32x16_bf16, splitting K: wave w takes the K steps
 // w, w + 4, w + 8, ... (16 each), so each wave's chain of dependent loads is
@@ -66,12 +75,15 @@ __device__ __forceinline__ float gelu_grad(float z)
 // 8(e/4) + 4(l/32) + e%4, column l%32 of the tile.
 constexpr int kGemmTile = 32;
 
-__global__ void __launch_bounds__(256) k_gemm_nt(GemmArgs g)
+__global__ void __launch_bounds__(256) k_gemm_nt(GemmPair gp)
 {
     __shared__ float part[3][16][64];       // waves 1..3: [element][lane]
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int m0 = blockIdx.y * kGemmTile;
-    const int n0 = blockIdx.x * kGemmTile;
+    const int second = (int)blockIdx.x >= gp.tiles0 ? 1 : 0;
+    const GemmArgs& g = gp.p[second];
+    const int t = (int)blockIdx.x - (second ? gp.tiles0 : 0);
+    const int m0 = (t / gp.ntn[second]) * kGemmTile;
+    const int n0 = (t % gp.ntn[second]) * kGemmTile;
     const int ra = m0 + (lane & 31), rb = n0 + (lane & 31);
     const int kk = 8 * (lane >> 5);
     const bool a_ok = ra < g.M, b_ok = rb < g.N;
@@ -192,50 +204,77 @@ __global__ void __launch_bounds__(256) k_mlp_loss_sum(const double* __restrict__
     if (threadIdx.x == 0) *loss = (float)(acc * scale);
 }
 
-// Bias gradients db[n] = sum_m dz[m][n] from the transposed copy; one wave per n.
-__global__ void __launch_bounds__(256) k_mlp_bias_grad(const __bf16* __restrict__ dzt, int lddzt, int M, int N,
-                                                       float* __restrict__ db)
+// Bias gradients of every layer in one launch: db_l[n] = sum_m dz_l[m][n]
+// from the transposed copies, one wave per n (fixed order: strided lane
+// sums, then the wave's butterfly).  Layer s has workgroups
+// [first[s], first[s + 1]), four columns each.
+struct BiasArgs {
+    const __bf16* dzt[kMaxLayers];
+    float* db[kMaxLayers];
+    int n[kMaxLayers];
+    int first[kMaxLayers + 1];
+    int nseg, lddzt, M;
+};
+
+__global__ void __launch_bounds__(256) k_mlp_bias_grad(BiasArgs a)
 {
-    const int n = blockIdx.x * 4 + (threadIdx.x >> 6);
+    int s = 0;
+    while (s + 1 < a.nseg && (int)blockIdx.x >= a.first[s + 1]) ++s;
+    const int n = ((int)blockIdx.x - a.first[s]) * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (n >= N) return;
-    float s = 0.0f;
-    for (int m = lane; m < M; m += 64) s += (float)dzt[(size_t)n * lddzt + m];
+    if (n >= a.n[s]) return;
+    const __bf16* dzt = a.dzt[s];
+    float acc = 0.0f;
+    for (int m = lane; m < a.M; m += 64) acc += (float)dzt[(size_t)n * a.lddzt + m];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if (lane == 0) db[n] = s;
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) a.db[s][n] = acc;
 }
 
-// AdamW (decoupled weight decay) on FP32 master weights [N][ld] (and a bias
-// when wbf == nullptr); refreshes the bf16 copies [N][ld] and [ld][ldT].
-struct AdamArgs {
+// AdamW (decoupled weight decay) on FP32 master weights, every tensor of the
+// network in one launch.  Segment s is a weight matrix [N][ld] (refreshing
+// its bf16 copies [N][ld] and [ld][ldT]) or a bias (wbf == nullptr, no
+// decay); its workgroups are blocks [first[s], first[s + 1]).
+constexpr int kAdamMaxSegs = 2 * kMaxLayers;
+
+struct AdamSeg {
     float* w;
     const float* g;
     float* m;
     float* v;
     __bf16* wbf;
     __bf16* wtbf;
-    int rows, cols, ld, ldT, count;
-    float lr, b1, b2, eps, wd, c1, c2;   // c1 = 1 - b1^t, c2 = 1 - b2^t
+    int ld, ldT, count;
+    float wd;
 };
 
-__global__ void k_adamw(AdamArgs a)
+struct AdamArgs {
+    AdamSeg seg[kAdamMaxSegs];
+    int first[kAdamMaxSegs + 1];
+    int nseg;
+    float lr, b1, b2, eps, c1, c2;   // c1 = 1 - b1^t, c2 = 1 - b2^t
+};
+
+__global__ void __launch_bounds__(256) k_adamw(AdamArgs a)
 {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= a.count) return;
-    const float g = a.g[idx];
-    const float m = a.b1 * a.m[idx] + (1.0f - a.b1) * g;
-    const float v = a.b2 * a.v[idx] + (1.0f - a.b2) * g * g;
-    a.m[idx] = m;
-    a.v[idx] = v;
+    int s = 0;
+    while (s + 1 < a.nseg && (int)blockIdx.x >= a.first[s + 1]) ++s;
+    const AdamSeg& q = a.seg[s];
+    const int idx = ((int)blockIdx.x - a.first[s]) * blockDim.x + threadIdx.x;
+    if (idx >= q.count) return;
+    const float g = q.g[idx];
+    const float m = a.b1 * q.m[idx] + (1.0f - a.b1) * g;
+    const float v = a.b2 * q.v[idx] + (1.0f - a.b2) * g * g;
+    q.m[idx] = m;
+    q.v[idx] = v;
     const float mh = m / a.c1, vh = v / a.c2;
-    float w = a.w[idx];
-    w -= a.lr * (mh / (sqrtf(vh) + a.eps) + a.wd * w);
-    a.w[idx] = w;
-    if (a.wbf) {
-        const int r = idx / a.ld, c = idx % a.ld;
-        a.wbf[idx] = (__bf16)w;
-        a.wtbf[(size_t)c * a.ldT + r] = (__bf16)w;
+    float w = q.w[idx];
+    w -= a.lr * (mh / (sqrtf(vh) + a.eps) + q.wd * w);
+    q.w[idx] = w;
+    if (q.wbf) {
+        const int r = idx / q.ld, c = idx % q.ld;
+        q.wbf[idx] = (__bf16)w;
+        q.wtbf[(size_t)c * q.ldT + r] = (__bf16)w;
     }
 }
 
@@ -288,10 +327,26 @@ int mfail(fk_mlp* n, hipError_t e, const char* what)
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
-void launch_gemm(const fk_mlp* n, const GemmArgs& g)
+int gemm_tiles(const GemmArgs& g, int* ntn)
 {
-    dim3 grid((g.N + kGemmTile - 1) / kGemmTile, (g.M + kGemmTile - 1) / kGemmTile);
-    hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, n->stream, g);
+    *ntn = (g.N + kGemmTile - 1) / kGemmTile;
+    return *ntn * ((g.M + kGemmTile - 1) / kGemmTile);
+}
+
+// one product, or two independent ones in the same launch
+void launch_gemm(const fk_mlp* n, const GemmArgs& g, const GemmArgs* g2 = nullptr)
+{
+    GemmPair gp{};
+    gp.p[0] = g;
+    gp.tiles0 = gemm_tiles(g, &gp.ntn[0]);
+    int tiles = gp.tiles0;
+    if (g2) {
+        gp.p[1] = *g2;
+        tiles += gemm_tiles(*g2, &gp.ntn[1]);
+    } else {
+        gp.ntn[1] = 1;
+    }
+    hipLaunchKernelGGL(k_gemm_nt, dim3(tiles), dim3(256), 0, n->stream, gp);
 }
 
 }  // namespace
@@ -481,9 +536,7 @@ extern "C" int fk_mlp_backward(fk_mlp* n, const float* target, int M, float* los
         g.out = n->gw[l - 1];
         g.ldout = n->pad[l - 1];
         g.epi = EPI_WGRAD;
-        launch_gemm(n, g);
-        hipLaunchKernelGGL(k_mlp_bias_grad, dim3((n->pad[l] + 3) / 4), dim3(256), 0, n->stream, n->dzT[l], mb, M,
-                           n->pad[l], n->gb[l - 1]);
+        if (l == 1) launch_gemm(n, g);
         if (l > 1) {
             // gradient of the pre-activation of layer l-1: dZ_{l-1} = (dZ_l W_l) * gelu'(Z_{l-1})
             GemmArgs d{};
@@ -501,8 +554,24 @@ extern "C" int fk_mlp_backward(fk_mlp* n, const float* target, int M, float* los
             d.actT = n->dzT[l - 1];
             d.ldactT = mb;
             d.epi = EPI_DGRAD;
-            launch_gemm(n, d);
+            launch_gemm(n, g, &d);
         }
+    }
+    {
+        // the bias gradients of all layers, from the dZ^T copies kept above
+        BiasArgs b{};
+        b.lddzt = mb;
+        b.M = M;
+        int blocks = 0;
+        for (int l = 1; l <= L; ++l) {
+            b.dzt[b.nseg] = n->dzT[l];
+            b.db[b.nseg] = n->gb[l - 1];
+            b.n[b.nseg] = n->pad[l];
+            b.first[b.nseg++] = blocks;
+            blocks += (n->pad[l] + 3) / 4;
+        }
+        b.first[b.nseg] = blocks;
+        hipLaunchKernelGGL(k_mlp_bias_grad, dim3(blocks), dim3(256), 0, n->stream, b);
     }
     FK_MHIP(n, hipGetLastError());
     if (loss_host) {
@@ -516,37 +585,42 @@ extern "C" int fk_mlp_adamw(fk_mlp* n, double lr, double beta1, double beta2, do
                             int64_t step)
 {
     if (!n || step < 1) return FK_E_INVALID;
+    AdamArgs a{};
+    a.lr = (float)lr;
+    a.b1 = (float)beta1;
+    a.b2 = (float)beta2;
+    a.eps = (float)eps;
+    a.c1 = (float)(1.0 - std::pow(beta1, (double)step));
+    a.c2 = (float)(1.0 - std::pow(beta2, (double)step));
+    int blocks = 0;
     for (int l = 0; l < n->L; ++l) {
-        AdamArgs a{};
-        a.lr = (float)lr;
-        a.b1 = (float)beta1;
-        a.b2 = (float)beta2;
-        a.eps = (float)eps;
-        a.c1 = (float)(1.0 - std::pow(beta1, (double)step));
-        a.c2 = (float)(1.0 - std::pow(beta2, (double)step));
-        a.w = n->w[l];
-        a.g = n->gw[l];
-        a.m = n->mw[l];
-        a.v = n->vw[l];
-        a.wbf = n->wbf[l];
-        a.wtbf = n->wtbf[l];
-        a.ld = n->pad[l];
-        a.ldT = n->pad[l + 1];
-        a.count = n->pad[l + 1] * n->pad[l];
-        a.wd = (float)weight_decay;
-        hipLaunchKernelGGL(k_adamw, dim3((a.count + 255) / 256), dim3(256), 0, n->stream, a);
-        AdamArgs c = a;   // biases: no weight decay, no bf16 copies
-        c.w = n->b[l];
-        c.g = n->gb[l];
-        c.m = n->mb[l];
-        c.v = n->vb[l];
-        c.wbf = nullptr;
-        c.wtbf = nullptr;
-        c.count = n->pad[l + 1];
-        c.ld = 1;
-        c.wd = 0.0f;
-        hipLaunchKernelGGL(k_adamw, dim3((c.count + 255) / 256), dim3(256), 0, n->stream, c);
+        AdamSeg& w = a.seg[a.nseg];
+        w.w = n->w[l];
+        w.g = n->gw[l];
+        w.m = n->mw[l];
+        w.v = n->vw[l];
+        w.wbf = n->wbf[l];
+        w.wtbf = n->wtbf[l];
+        w.ld = n->pad[l];
+        w.ldT = n->pad[l + 1];
+        w.count = n->pad[l + 1] * n->pad[l];
+        w.wd = (float)weight_decay;
+        a.first[a.nseg++] = blocks;
+        blocks += (w.count + 255) / 256;
+        AdamSeg& b = a.seg[a.nseg];   // bias: no weight decay, no bf16 copies
+        b.w = n->b[l];
+        b.g = n->gb[l];
+        b.m = n->mb[l];
+        b.v = n->vb[l];
+        b.ld = 1;
+        b.ldT = 1;
+        b.count = n->pad[l + 1];
+        b.wd = 0.0f;
+        a.first[a.nseg++] = blocks;
+        blocks += (b.count + 255) / 256;
     }
+    a.first[a.nseg] = blocks;
+    hipLaunchKernelGGL(k_adamw, dim3(blocks), dim3(256), 0, n->stream, a);
     FK_MHIP(n, hipGetLastError());
     return FK_OK;
 }

@@ -227,8 +227,9 @@ struct fk_ctx {
     std::vector<fk_state> history;
     int64_t drained_step = -1;    // last step whose record has been drained
     // profiling
-    bool prof = false;
-    struct Ev { hipEvent_t a, b; };   // sweep launch a->b
+    int prof = 0;                  // 0: off; n: events around every n-th step
+    int64_t prof_count = 0;        // steps launched since profiling was switched on
+    struct Ev { hipEvent_t a, b, c; };   // sweep launch a->b, reduction and field b->c
     std::vector<Ev> events;
     std::vector<hipEvent_t> spare;
     std::vector<int> tile_order;   // host copy of the tile list (kept alive for the async upload)
@@ -274,6 +275,13 @@ SweepArgs<T> sweep_args(const fk_ctx* c, int from)
     a.dt_dx = c->L.dt / c->L.dx;
     a.dy = c->L.dy;
     a.x_on = (c->p.physics_mask & FK_PHYS_X) ? 1 : 0;
+    // non-temporal stores pay when every row of f starts on a 128-byte line,
+    // so that each wave writes whole lines; a row that shares lines with its
+    // neighbours is better merged in L2 first
+    const bool rows_on_lines = ((size_t)c->p.nvy * sizeof(T)) % 128 == 0 &&
+                               reinterpret_cast<uintptr_t>(c->b.f[0]) % 128 == 0 &&
+                               reinterpret_cast<uintptr_t>(c->b.f[1]) % 128 == 0;
+    a.store_nt = rows_on_lines ? 1 : 0;
     a.tile_list = c->b.tiles;
     a.n_list = c->L.n_it;
     return a;
@@ -522,7 +530,7 @@ int capture_graphs(fk_ctx* c)
         hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
         if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
         e = hipGraphInstantiate(&c->graph[start], g, nullptr, nullptr, 0);
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
         if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
     }
     c->graph_ready = true;
@@ -596,6 +604,7 @@ void release(fk_ctx* c)
     for (auto& e : c->events) {
         (void)hipEventDestroy(e.a);
         (void)hipEventDestroy(e.b);
+        (void)hipEventDestroy(e.c);
     }
     for (auto e : c->spare) (void)hipEventDestroy(e);
     if (c->own_f) {
@@ -781,17 +790,22 @@ extern "C" int fk_step(fk_ctx* c, int64_t n)
     if (c->batch_member) return set_error(&c->err, FK_E_STATE, "a batch member is stepped through fk_batch_step");
     if (c->sticky) return c->sticky;
     if (c->prof) {
-        // two events per step, around the sweep launch only; the interval
-        // from one step's sweep end to the next step's sweep start holds the
-        // reduction and field kernels
+        // direct launches; a sampled step gets three events: before and
+        // after its sweep launch and after its reduction and field kernels
         for (int64_t s = 0; s < n; ++s) {
-            hipEvent_t e0 = get_event(c), e1 = get_event(c);
-            if (!e0 || !e1) return set_error(&c->err, FK_E_HIP, "hipEventCreate failed");
+            if (c->prof_count++ % c->prof != 0) {
+                enqueue_step(c, c->cur, c->stream);
+                c->cur ^= 1;
+                continue;
+            }
+            hipEvent_t e0 = get_event(c), e1 = get_event(c), e2 = get_event(c);
+            if (!e0 || !e1 || !e2) return set_error(&c->err, FK_E_HIP, "hipEventCreate failed");
             FK_HIP(c, hipEventRecord(e0, c->stream));
             launch_sweep(c, c->cur, c->stream);
             FK_HIP(c, hipEventRecord(e1, c->stream));
             launch_field(c, 1, c->stream);
-            c->events.push_back({e0, e1});
+            FK_HIP(c, hipEventRecord(e2, c->stream));
+            c->events.push_back({e0, e1, e2});
             c->cur ^= 1;
         }
         FK_HIP(c, hipGetLastError());
@@ -925,16 +939,18 @@ extern "C" int fk_saturated(fk_ctx* c, double window_s, double rtol, int* out)
     return fk_saturation_check(c->history.data(), c->history.size(), window_s, rtol, out);
 }
 
-extern "C" int fk_set_profiling(fk_ctx* c, int on)
+extern "C" int fk_set_profiling(fk_ctx* c, int every)
 {
-    if (!c) return FK_E_INVALID;
+    if (!c || every < 0) return FK_E_INVALID;
     FK_HIP(c, hipStreamSynchronize(c->stream));
     for (auto& e : c->events) {
         c->spare.push_back(e.a);
         c->spare.push_back(e.b);
+        c->spare.push_back(e.c);
     }
     c->events.clear();
-    c->prof = on != 0;
+    c->prof = every;
+    c->prof_count = 0;
     return FK_OK;
 }
 
@@ -944,16 +960,14 @@ extern "C" int fk_kernel_times(fk_ctx* c, double* sweep_ms, int64_t* sweep_n, do
     FK_HIP(c, hipStreamSynchronize(c->stream));
     double t[2] = {0, 0};
     int64_t n[2] = {0, 0};
-    for (size_t m = 0; m < c->events.size(); ++m) {
+    for (const auto& e : c->events) {
         float ms = 0;
-        FK_HIP(c, hipEventElapsedTime(&ms, c->events[m].a, c->events[m].b));
+        FK_HIP(c, hipEventElapsedTime(&ms, e.a, e.b));
         t[0] += ms;
         n[0] += 1;
-        if (m + 1 < c->events.size()) {
-            FK_HIP(c, hipEventElapsedTime(&ms, c->events[m].b, c->events[m + 1].a));
-            t[1] += ms;
-            n[1] += 1;
-        }
+        FK_HIP(c, hipEventElapsedTime(&ms, e.b, e.c));
+        t[1] += ms;
+        n[1] += 1;
     }
     if (sweep_ms) *sweep_ms = t[0];
     if (sweep_n) *sweep_n = n[0];
@@ -967,8 +981,8 @@ extern "C" int fk_autotune(fk_ctx* c, int trial_steps, fk_info* chosen)
     if (!c || trial_steps < 2) return FK_E_INVALID;
     if (c->batch_member) return set_error(&c->err, FK_E_STATE, "batch members are tuned by their batch");
     if (c->sticky) return c->sticky;
-    const bool prof = c->prof;
-    c->prof = false;
+    const int prof = c->prof;
+    c->prof = 0;
     size_t begin = 0;
     int rc = drain(c, &begin);
     if (rc && rc != FK_E_STATE) return rc;

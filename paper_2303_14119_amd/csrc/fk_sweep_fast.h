@@ -185,10 +185,18 @@ __device__ __forceinline__ void sweep_fast(const SweepArgs<T>& a, int it, int kc
 
         {
             const rsrc_t po = make_rsrc(a.fout + (size_t)k * plane, pbytes);
+            if (a.store_nt) {
 #pragma unroll
-            for (int r = 0; r < TI; ++r) {
-                if (RAGGED) bstore<T>(f3[r], po, roff(r + 1), 0);
-                else bstore<T>(f3[r], po, vb, r * rb);
+                for (int r = 0; r < TI; ++r) {
+                    if (RAGGED) bstore<T, kCpStream>(f3[r], po, roff(r + 1), 0);
+                    else bstore<T, kCpStream>(f3[r], po, vb, r * rb);
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < TI; ++r) {
+                    if (RAGGED) bstore<T>(f3[r], po, roff(r + 1), 0);
+                    else bstore<T>(f3[r], po, vb, r * rb);
+                }
             }
         }
 

@@ -285,8 +285,8 @@ class Solver:
         a = np.ascontiguousarray(profile, dtype=np.float64)
         self._chk(fk_warm_start(self._h, a.ctypes.data, a.size, 0, float(t_ev), int(step)))
 
-    def set_profiling(self, on=True):
-        self._chk(fk_set_profiling(self._h, 1 if on else 0))
+    def set_profiling(self, on=True, every=1):
+        self._chk(fk_set_profiling(self._h, int(every) if on else 0))
 
     def autotune(self, trial_steps=16):
         info = fk_info()

@@ -177,20 +177,23 @@ def test_checkpoint_resume_bitwise(fk):
 
 
 def test_profiled_steps_time_every_sweep_and_change_nothing(fk):
-    """With profiling on, every sweep launch is bracketed by HIP events
-    (direct launches) and the state is bitwise the same as without it."""
+    """With profiling on, the sampled steps' sweep launches and field kernels
+    are bracketed by HIP events (all steps launched directly), and the state
+    is bitwise the same as without profiling."""
     cfg = W.c0()
     f0 = W.random_state((cfg["nx"], cfg["nvx"], cfg["nvy"]), seed=2, scale=1e3).astype(np.float32)
     out = []
-    for prof in (False, True):
+    for every in (0, 1, 3):
         with fk.Solver(cfg, "f32") as s:
             s.write_state(f0, 1e-6)
-            s.set_profiling(prof)
-            s.step(40)
+            s.set_profiling(every > 0, every=every)
+            s.step(25)
+            s.step(15)
             s.sync()
-            if prof:
+            if every:
                 kt = s.kernel_times()
-                assert kt["sweep_n"] == 40 and kt["field_n"] == 39
+                want = 40 if every == 1 else 14      # steps 0, 3, ..., 39
+                assert kt["sweep_n"] == want and kt["field_n"] == want
                 assert kt["sweep_ms"] > 0 and kt["field_ms"] > 0
             out.append(s.f())
-    assert np.array_equal(out[0], out[1])
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
