@@ -482,18 +482,9 @@ __device__ __forceinline__ void plane_sums(const double* __restrict__ part_n, in
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nx) return;
-    // all loads of a chunk of tiles are issued before the first add, so a
-    // chunk costs one memory latency; the adds stay in tile order
-    constexpr int kChunk = 32;
     double s = 0.0;
-    for (int u0 = 0; u0 < n_it; u0 += kChunk) {
-        double v[kChunk];
-#pragma unroll
-        for (int q = 0; q < kChunk; ++q) v[q] = u0 + q < n_it ? part_n[(size_t)(u0 + q) * nx + k] : 0.0;
-#pragma unroll
-        for (int q = 0; q < kChunk; ++q)
-            if (u0 + q < n_it) s += v[q];
-    }
+#pragma unroll 16
+    for (int u = 0; u < n_it; ++u) s += part_n[(size_t)u * nx + k];
     plane_sum[k] = s;
 }
 
