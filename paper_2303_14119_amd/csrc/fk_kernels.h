@@ -514,6 +514,38 @@ struct FieldArgs {
 // keeps their densities in registers.  sh holds 2 * kFieldThreads doubles.
 constexpr int kFieldSegMax = 8;
 
+// Plane sums of planes kb .. kb + SEG - 1 (tiles in order) into n[0 .. SEG).
+// Either read from the reduced plane sums or added here from the tile
+// partials, four tiles' loads in flight before their adds.
+template <int SEG>
+__device__ __forceinline__ void plane_densities(const FieldArgs& a, int kb, double (&n)[kFieldSegMax])
+{
+    const int klast = a.nx - 1;
+#pragma unroll
+    for (int q = 0; q < kFieldSegMax; ++q) n[q] = 0.0;
+    if (a.plane_sum) {
+#pragma unroll
+        for (int q = 0; q < SEG; ++q) n[q] = a.plane_sum[min(kb + q, klast)];
+        return;
+    }
+    constexpr int kChunk = 4;
+    for (int u0 = 0; u0 < a.n_it; u0 += kChunk) {
+        double v[kChunk][SEG];
+#pragma unroll
+        for (int c = 0; c < kChunk; ++c) {
+            const double* row = a.part_n + (size_t)min(u0 + c, a.n_it - 1) * a.nx;
+#pragma unroll
+            for (int q = 0; q < SEG; ++q) v[c][q] = row[min(kb + q, klast)];
+        }
+#pragma unroll
+        for (int c = 0; c < kChunk; ++c)
+            if (u0 + c < a.n_it) {
+#pragma unroll
+                for (int q = 0; q < SEG; ++q) n[q] += v[c][q];
+            }
+    }
+}
+
 __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
 {
     const int t = threadIdx.x;
@@ -522,31 +554,26 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
     const int seg = (a.nx + T - 1) / T;
     const int kb = min(t * seg, a.nx), ke = min(kb + seg, a.nx);
     const DevState old = *a.st;     // issued early: needed after the scans
+    const double zsum = a.consts[0], inj_step = a.consts[2], emit_pref = a.consts[3];
 
+    // Every global load comes before the first global store: one counter
+    // tracks both, so a load waited for after a store waits for the store
+    // too.  Loads use clamped indices and stay unconditional (values past
+    // the thread's segment are dropped).
+    //
     // electron density per plane: sum over the v_x tiles in tile order
     double nloc[kFieldSegMax];
     double local = 0.0;
-    if (seg <= kFieldSegMax) {
-#pragma unroll
-        for (int q = 0; q < kFieldSegMax; ++q) nloc[q] = 0.0;
-        if (a.plane_sum) {
-#pragma unroll
-            for (int q = 0; q < kFieldSegMax; ++q)
-                if (kb + q < ke) nloc[q] = a.plane_sum[kb + q];
-        } else {
-#pragma unroll 4
-        for (int u = 0; u < a.n_it; ++u) {
-            const double* row = a.part_n + (size_t)u * a.nx;
-#pragma unroll
-            for (int q = 0; q < kFieldSegMax; ++q)
-                if (kb + q < ke) nloc[q] += row[kb + q];
-        }
-        }
+    const bool in_regs = seg <= kFieldSegMax;
+    if (in_regs) {
+        if (seg == 1) plane_densities<1>(a, kb, nloc);
+        else if (seg == 2) plane_densities<2>(a, kb, nloc);
+        else if (seg <= 4) plane_densities<4>(a, kb, nloc);
+        else plane_densities<kFieldSegMax>(a, kb, nloc);
 #pragma unroll
         for (int q = 0; q < kFieldSegMax; ++q)
             if (kb + q < ke) {
                 nloc[q] *= a.dv2;
-                a.ne[kb + q] = nloc[q];
                 local += nloc[q];
             }
     } else {
@@ -620,10 +647,13 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
         cmax = fmax(cmax, fabs(d));
         run += nk;
     };
-    if (seg <= kFieldSegMax) {
+    if (in_regs) {
 #pragma unroll
         for (int q = 0; q < kFieldSegMax; ++q)
-            if (kb + q < ke) field_at(kb + q, nloc[q]);
+            if (kb + q < ke) {
+                a.ne[kb + q] = nloc[q];
+                field_at(kb + q, nloc[q]);
+            }
     } else {
         for (int k = kb; k < ke; ++k) field_at(k, a.ne[k]);
     }
@@ -647,18 +677,17 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
         const double g_pe = x_on ? pe * a.dv2 : 0.0;
         const double g_see = see_on ? see * a.dv2 : 0.0;
         const double g_top = x_on ? top * a.dv2 : 0.0;
-        const double zsum = a.consts[0];
         double gscale = 0.0;
         if (see_on) {
             if (a.emission_norm == FK_EMIT_DISCRETE) gscale = zsum > 0.0 ? g_see / zsum : 0.0;
-            else gscale = g_see * a.consts[3];
+            else gscale = g_see * emit_pref;
         }
         const double emitted = gscale * zsum;
         const double n_total = total * a.dx;
         const double loss_v = a.advance ? lv * a.dx * a.dv2 : 0.0;
         double resid = 0.0;
         if (a.advance) {
-            const double inj = (a.mask & FK_PHYS_SRC) ? a.consts[2] : 0.0;
+            const double inj = (a.mask & FK_PHYS_SRC) ? inj_step : 0.0;
             resid = (n_total - old.n_total) - (a.dt * (old.emitted - old.g_pe - old.g_top) + inj - loss_v);
         }
         DevState ns = old;
