@@ -22,7 +22,7 @@ int set_error(std::string* slot, int code, const std::string& msg)
 static size_t sweep_lds(int ti, int block, int kc, int elem)
 {
     const int waves = (block + 63) / 64;
-    return (size_t)2 * ti * (block + 2) * elem + (size_t)kc * waves * 8 + (size_t)waves * 4 * 8;
+    return (size_t)2 * ti * (block + 2) * elem + (size_t)kc * waves * 8 + (size_t)waves * 4 * 8 + (size_t)waves * 2 * kc * elem;
 }
 
 int derive_layout(const fk_params* p, Layout* L, std::string* why)

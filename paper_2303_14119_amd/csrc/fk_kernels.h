@@ -254,27 +254,39 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, int it, int kc
 #pragma unroll
         for (int r = 0; r < TI + 2; ++r) fc[r] = bload<T>(pr, vo[r], 0);
     }
+    // Loads without branches (exact wait counts for the compiler): a plane
+    // past x = L gets an empty descriptor and reads 0 (nothing enters there,
+    // Eq 17), and rows that must not read the plane get an out-of-range
+    // lane offset.  Past k1 only the rows with v_x < 0 read the plane.
     auto load_ahead = [&](int kk, T (&dst)[TI + 2]) {
-        if (kk < k1) {
-            const rsrc_t pr = plane_in(kk);
+        const bool in = kk < a.nx, inner = kk < k1;
+        const rsrc_t pr = make_rsrc(a.fin + (size_t)(in ? kk : 0) * plane, in ? pbytes : 0u);
 #pragma unroll
-            for (int r = 0; r < TI + 2; ++r) dst[r] = bload<T>(pr, vo[r], 0);
-        } else if (kk < a.nx) {
-            const rsrc_t pr = plane_in(kk);
-#pragma unroll
-            for (int r = 0; r < TI + 2; ++r) dst[r] = down_row(r) ? bload<T>(pr, vo[r], 0) : T(0);
-        } else {
-#pragma unroll
-            for (int r = 0; r < TI + 2; ++r) dst[r] = T(0);   // nothing enters at x = L (Eq 17)
-        }
+        for (int r = 0; r < TI + 2; ++r)
+            dst[r] = bload<T>(pr, (inner || down_row(r)) ? vo[r] : kIdleLaneOffset, 0);
     };
     load_ahead(k0 + 1, fp);
 
     double lv = 0.0, spe = 0.0, ssee = 0.0, stop = 0.0;
     const T dy = T(a.dy);
 
+    // the planes' v_x Courant numbers and source coefficients (used in T
+    // precision only), staged per wave in LDS: the plane loop then issues no
+    // memory operation but its plane loads and stores, so the compiler's
+    // waits for the prefetched plane never cover a later load.  A wave reads
+    // only what its own lanes wrote, so no workgroup barrier is needed.
+    T* tab = reinterpret_cast<T*>(red + nw * 4) + wave * 2 * a.kc;   // [nw][2][kc]
+    for (int m = lane; m < k1 - k0; m += 64) {
+        tab[m] = T(a.dxk[k0 + m]);
+        tab[a.kc + m] = T(a.srck[k0 + m]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     for (int k = k0; k < k1; ++k) {
-        if (k + 2 <= k1) load_ahead(k + 2, fn);
+        const T d_k = tab[k - k0];
+        const T s_k = tab[a.kc + k - k0];
+        load_ahead(k + 2, fn);   // reads nothing useful on the last iteration
 
         // x sweep: f' = f - c (f - f_up), upwind on the sign of v_x
         T f1[TI + 2];
@@ -282,7 +294,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, int it, int kc
         for (int r = 0; r < TI + 2; ++r) f1[r] = fc[r] - cp[r] * (fc[r] - fm[r]) - cn[r] * (fp[r] - fc[r]);
 
         // v_x sweep by a_x(x_k): upwind on the sign of the plane's Courant number
-        const T d = T(a.dxk[k]);
+        const T d = T(d_k);
         T f2[TI];
 #pragma unroll
         for (int r = 1; r <= TI; ++r) {
@@ -320,9 +332,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, int it, int kc
         }
 
         // band source (Eq 7)
-        const double s = a.srck[k];
-        if (s != 0.0) {
-            const T ts = T(s);
+        if (s_k != 0) {
+            const T ts = T(s_k);
 #pragma unroll
             for (int r = 0; r < TI; ++r)
                 if (rv[r + 1] && jok) f3[r] += ts * a.fsrc[(size_t)(i0 + r) * a.nvy + j];

@@ -1178,7 +1178,7 @@ int bfail(fk_batch* b, hipError_t e, const char* what)
 size_t batch_slice_doubles(int ti, int block, int kc)
 {
     const int waves = block / 64;
-    const size_t bytes = (size_t)2 * ti * (block + 2) * 4 + (size_t)kc * waves * 8 + (size_t)waves * 32;
+    const size_t bytes = (size_t)2 * ti * (block + 2) * 4 + (size_t)kc * waves * 8 + (size_t)waves * 32 + (size_t)waves * 2 * kc * 4;
     return (bytes + 7) / 8;
 }
 

@@ -106,20 +106,34 @@ __device__ __forceinline__ void sweep_fast(const SweepArgs<T>& a, int it, int kc
     double lv = 0.0, spe = 0.0, ssee = 0.0, stop = 0.0;
     const rsrc_t psrc = make_rsrc(a.fsrc, pbytes);
 
+    // the planes' v_x Courant numbers and source coefficients (used in T
+    // precision only), staged per wave in LDS: the plane loop then issues no
+    // memory operation but its plane loads and stores, so the compiler's
+    // waits for the prefetched plane never cover a later load.  A wave reads
+    // only what its own lanes wrote, so no workgroup barrier is needed.
+    T* tab = reinterpret_cast<T*>(red + nw * 4) + wave * 2 * a.kc;   // [nw][2][kc]
+    for (int m = lane; m < k1 - k0; m += 64) {
+        tab[m] = T(a.dxk[k0 + m]);
+        tab[a.kc + m] = T(a.srck[k0 + m]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     for (int k = k0; k < k1; ++k) {
-        // prefetch the planes of the next iteration
-        if (k + 1 < k1) {
-            const rsrc_t p1 = plane_in(k + 1);
+        const T d_k = tab[k - k0];
+        const T s_k = tab[a.kc + k - k0];
+        // prefetch the planes of the next iteration.  The loads are issued on
+        // every iteration (no branch, so the compiler's wait counts stay
+        // exact); a plane that does not exist gets an empty descriptor and
+        // reads 0, as nothing enters at x = L (Eq 17)
+        {
+            const bool n1 = k + 1 < k1, n2 = n1 && k + 2 < a.nx;
+            const rsrc_t p1 = make_rsrc(a.fin + (size_t)(n1 ? k + 1 : k) * plane, n1 ? pbytes : 0u);
+            const rsrc_t p2 = make_rsrc(a.fin + (size_t)(n2 ? k + 2 : k) * plane, n2 ? pbytes : 0u);
 #pragma unroll
             for (int r = S; r < TI + 2; ++r) w2[r] = ldrow(p1, r);
-            if (k + 2 < a.nx) {
-                const rsrc_t p2 = plane_in(k + 2);
 #pragma unroll
-                for (int r = 0; r < S; ++r) w2[r] = ldrow(p2, r);
-            } else {
-#pragma unroll
-                for (int r = 0; r < S; ++r) w2[r] = T(0);
-            }
+            for (int r = 0; r < S; ++r) w2[r] = ldrow(p2, r);
         }
 
         // x sweep (upwind on the sign of v_x)
@@ -129,7 +143,7 @@ __device__ __forceinline__ void sweep_fast(const SweepArgs<T>& a, int it, int kc
             f1[r] = r < S ? w0[r] - c[r] * (w1[r] - w0[r]) : w1[r] - c[r] * (w1[r] - w0[r]);
 
         // v_x sweep by a_x(x_k), upwind on the sign of the plane's Courant number
-        const T d = T(a.dxk[k]);
+        const T d = T(d_k);
         T f2[TI];
         if (d > T(0)) {
 #pragma unroll
@@ -175,9 +189,8 @@ __device__ __forceinline__ void sweep_fast(const SweepArgs<T>& a, int it, int kc
         }
 
         // band source (Eq 7)
-        const double s = a.srck[k];
-        if (s != 0.0) {
-            const T ts = T(s);
+        if (s_k != 0) {
+            const T ts = T(s_k);
 #pragma unroll
             for (int r = 0; r < TI; ++r)
                 f3[r] += ts * (RAGGED ? bload<T>(psrc, roff(r + 1), 0) : bload<T>(psrc, vb, r * rb));
