@@ -678,19 +678,25 @@ int sweep_wgs_per_cu(const Layout& L)
     return e == hipSuccess ? occ : 0;
 }
 
-// x planes per tile when the caller leaves it open: among 16 .. 128 (steps
-// of 8), the count whose workgroups fill the last round of the device's
-// workgroup slots best (compute units x workgroups per unit), the longest
-// on ties.  With one 6-wave workgroup per unit (384 v_y lanes, 16-row
-// tiles) a 4.03-round launch ran 14% slower than a whole number of rounds.
+// x planes per tile when the caller leaves it open, among 16 .. 128 (steps
+// of 8).  The pick is the longest x run whose launch keeps at least 8 waves
+// resident on every compute unit (2 per SIMD, or all that a unit can hold
+// if that is fewer) and spreads its workgroups evenly: the last round of
+// the device's workgroup slots (or, below one round, each unit's share) as
+// full as any other candidate's.  With the prefetch overlapped, more waves
+// than that only add concurrent streams: at 2048 x 256 x 256, 2 workgroups
+// of 4 waves per unit (128 planes) beat 4 (64 planes) by 7%, while 150 v_y
+// lanes (3-wave workgroups) needed the 4.  A launch of 4.03 rounds of
+// one 6-wave workgroup per unit ran 14% slower than a whole number.  Grids
+// too small for the wave target fall back to the fullest last round.
 void choose_planes(const fk_params* p, Layout* L)
 {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         cus < 1)
         return;
-    double best = -1.0;
-    Layout pick = *L;
+    double best = -1.0, best_fill = -1.0;
+    Layout pick = *L, pick_fill = *L;
     for (int kc = 16; kc <= 128 && kc <= std::max(16, p->nx); kc += 8) {
         fk_params q = *p;
         q.tile_rows = L->ti;
@@ -699,15 +705,25 @@ void choose_planes(const fk_params* p, Layout* L)
         if (derive_layout(&q, &t, nullptr) != FK_OK) continue;
         const int occ = sweep_wgs_per_cu(t);
         if (occ < 1) continue;
+        const int wpw = (t.block + 63) / 64;
         const double slots = (double)cus * occ;
-        const double rounds = std::ceil(t.nwg / slots);
-        const double fill = t.nwg / (rounds * slots);
-        if (fill >= best - 1e-9) {     // ties go to the longer x runs (later kc)
-            best = fill;
+        const double rounds = t.nwg / slots;
+        const double fill = t.nwg / (std::ceil(rounds) * slots);
+        if (fill >= best_fill - 1e-9) {    // ties go to the longer x runs (later kc)
+            best_fill = fill;
+            pick_fill = t;
+        }
+        const double per_cu = (double)t.nwg / cus;
+        const int resident = std::min((int)per_cu, occ) * wpw;
+        if (resident < std::min(8, occ * wpw)) continue;
+        const double even = rounds >= 1.0 ? fill : per_cu / std::ceil(per_cu);
+        if (even >= best - 1e-9) {
+            best = even;
             pick = t;
         }
     }
     if (best > 0.0) *L = pick;
+    else if (best_fill > 0.0) *L = pick_fill;
     (void)hipGetLastError();
 }
 
