@@ -77,14 +77,16 @@ def cpu_baseline(cfg, budget_s=12.0):
 
 
 def bench_batch(args):
-    """64 uneven instances (seed 0) in one persistent launch per step:
-    Gcell-updates/s over args.steps steps after args.warmup steps."""
+    """64 uneven instances (seed 0), tiling and launch mode picked by the
+    library's autotuner at creation (not timed): Gcell-updates/s over
+    args.steps steps after args.warmup steps."""
     import torch
     from paper_2303_14119_amd import flashkin as fk
     from paper_2303_14119_amd import workloads as W
     torch.cuda.init()
     stream = torch.cuda.current_stream().cuda_stream
-    b = fk.Batch(W.c2_instances(seed=0, n=64), stream=stream, trace_cap=16, trace_stride=1000)
+    b = fk.Batch(W.c2_instances(seed=0, n=64), stream=stream, trace_cap=16, trace_stride=1000,
+                 autotune=not args.batch_default)
     info = b.info()
     b.step(args.warmup)
     torch.cuda.synchronize()
@@ -101,7 +103,9 @@ def bench_batch(args):
                       "warmup": args.warmup, "ms_per_step": round(el * 1e3 / args.steps, 4),
                       "hbm_frac_algorithmic": round(8.0 * v * 1e9 / (HBM_PEAK_GBS * 1e9), 4),
                       "cells": info["cells"], "instances": info["n"], "flagged_instances": flagged,
-                      "tile_rows": info["tile_rows"], "tile_planes": info["tile_planes"]}), flush=True)
+                      "tile_rows": info["tile_rows"], "tile_planes": info["tile_planes"],
+                      "autotuned": not args.batch_default, "sweep_launches_per_step": info["sweep_launches"],
+                      "persistent_grid": info["grid"], "schedule": info["schedule"]}), flush=True)
 
 
 def bench_mlp(args):
@@ -147,6 +151,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--batch-default", action="store_true",
+                    help="batch mode: the default tiling and split launches instead of the autotuned choice")
     ap.add_argument("--sample-every", type=int, default=4,
                     help="HIP events around every n-th step's kernels in the timed region")
     ap.add_argument("--pre-steps", type=int, default=3000,
