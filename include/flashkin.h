@@ -96,7 +96,7 @@ typedef struct {
     int32_t trace_stride;    /* record observables every trace_stride steps (>= 1) */
     int32_t trace_cap;       /* records held on the device between drains (>= 1) */
     int32_t tile_rows;       /* v_x rows per tile, 0 = library choice */
-    int32_t tile_planes;     /* x planes per tile; 0: chosen at creation so the sweep launch fills whole rounds of the device's workgroup slots (fk_validate reports a host-side estimate, fk_query the choice) */
+    int32_t tile_planes;     /* x planes per tile; 0: chosen at creation from the sweep kernel's occupancy: the longest run (16..128) that keeps 8 waves resident per compute unit, or all a unit holds, with the workgroups spread evenly (fk_validate reports a host-side estimate, fk_query the choice); batch instances get 16 */
 } fk_params;
 
 /* Observables of the state (f^n, sigma^n) after n steps.  The fluxes are
@@ -246,13 +246,13 @@ int fk_autotune(fk_ctx* ctx, int trial_steps, fk_info* chosen);
  * field launch then reduces and solves every instance (a workgroup each);
  * steps are replayed from HIP graphs.  Every instance is FK_F32 with
  * nvy <= 256 and starts at f = 0, sigma = 0.
- *   mode 0: split launches (default): up to four sweep launches per step,
- *           by tile body and workgroup width, each with its own register
- *           budget;
+ *   mode 0: split launches: up to four sweep launches per step, by tile
+ *           body and workgroup width;
  *   mode 1: autotune: time short trial runs of tilings, grid sizes, item
  *           schedules and both launch modes, keep the fastest, then reset
  *           the instances to f = 0;
- *   mode 2: one sweep launch per step for all instances and tiles.
+ *   mode 2: one sweep launch per step for all instances and tiles (on
+ *           64 uneven instances the faster of the two untuned modes).
  * Results are bitwise the same in every mode and equal to single contexts
  * with the same tiling. */
 typedef struct {

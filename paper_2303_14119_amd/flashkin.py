@@ -320,10 +320,10 @@ class View(Solver):
 
 class Batch:
     """Independent FP32 instances stepped together by persistent launches
-    (fk_batch_*): split launches by default, one sweep launch per step with
-    ``single_launch``, or whichever of the two ``autotune`` finds faster."""
+    (fk_batch_*): one sweep launch per step by default, split launches with
+    ``single_launch=False``, or whatever ``autotune`` finds fastest."""
 
-    def __init__(self, cfgs, stream=None, autotune=False, trace_stride=1, single_launch=False, **kw):
+    def __init__(self, cfgs, stream=None, autotune=False, trace_stride=1, single_launch=True, **kw):
         self.cfgs = list(cfgs)
         strides = trace_stride if isinstance(trace_stride, (list, tuple)) else [trace_stride] * len(self.cfgs)
         arr = (fk_params * len(self.cfgs))(*[make_params(c, "f32", trace_stride=st, **kw)
