@@ -105,7 +105,8 @@ def bench_batch(args):
                       "cells": info["cells"], "instances": info["n"], "flagged_instances": flagged,
                       "tile_rows": info["tile_rows"], "tile_planes": info["tile_planes"],
                       "autotuned": not args.batch_default, "sweep_launches_per_step": info["sweep_launches"],
-                      "persistent_grid": info["grid"], "schedule": info["schedule"]}), flush=True)
+                      "persistent_grid": info["grid"], "schedule": info["schedule"],
+                      "workgroup_threads": info["single_threads"] or None}), flush=True)
 
 
 def bench_mlp(args):

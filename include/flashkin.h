@@ -249,10 +249,14 @@ int fk_autotune(fk_ctx* ctx, int trial_steps, fk_info* chosen);
  *   mode 0: split launches: up to four sweep launches per step, by tile
  *           body and workgroup width;
  *   mode 1: autotune: time short trial runs of tilings, grid sizes, item
- *           schedules and both launch modes, keep the fastest, then reset
- *           the instances to f = 0;
- *   mode 2: one sweep launch per step for all instances and tiles (on
- *           64 uneven instances the faster of the two untuned modes).
+ *           schedules and both launch modes (mode 2 at 256 and at 192
+ *           threads per workgroup), keep the fastest, then reset the
+ *           instances to f = 0;
+ *   mode 2: one sweep launch per step for all instances and tiles, in
+ *           workgroups of 256 threads (on 64 uneven instances the faster
+ *           of the untuned modes);
+ *   mode 3: as mode 2 with workgroups of 192 threads (no idle wave beside
+ *           a 192-lane v_y block), or 256 if an instance has nvy > 192.
  * Results are bitwise the same in every mode and equal to single contexts
  * with the same tiling. */
 typedef struct {
@@ -265,6 +269,7 @@ typedef struct {
     int64_t cells;         /* sum of nx * nvx * nvy over the instances */
     int32_t schedule;      /* 0: items from an atomic counter, 1: static round-robin */
     int32_t sweep_launches;/* sweep launches per step (1 in mode 2) */
+    int32_t single_threads;/* threads per workgroup of the single sweep launch (256, or 192 if the autotuner chose it); 0 with split launches */
 } fk_batch_info_t;
 
 int fk_batch_create(const fk_params* params, int n, void* stream, int mode, fk_batch** out);

@@ -1163,6 +1163,8 @@ struct fk_batch {
     int ti = 8;
     int sched = 0;                // 0 dynamic (atomic counter), 1 static round-robin
     int single = 0;               // 1: one sweep launch per step (class 4 only)
+    int single_width = 0;         // threads per workgroup of that launch asked for: 192, or 0 (256)
+    int single_threads = 256;     // the width in use
     int occ = 0;                  // workgroups per compute unit (0 = occupancy limit)
     std::vector<char> active;     // instances still stepped
     int n_active = 0;
@@ -1201,13 +1203,15 @@ size_t batch_slice_doubles(int ti, int block, int kc)
     return (bytes + 7) / 8;
 }
 
+int batch_threads(const fk_batch* b, int k) { return k == 4 ? b->single_threads : class_threads(k); }
+
 template <int TI>
 void batch_launch_sweeps(const fk_batch* b, int from, hipStream_t s)
 {
     for (int k = 0; k < kBatchClasses; ++k) {
         if (b->cls_n[k] == 0) continue;
         const BatchItem* items = b->d_items + b->cls_off[k];
-        const dim3 grid(b->cls_grid[k]), block(class_threads(k));
+        const dim3 grid(b->cls_grid[k]), block(batch_threads(b, k));
         int* ctr = b->d_counter + k;
         switch (class_body(k)) {
         case BODY_FAST:
@@ -1234,9 +1238,8 @@ void batch_launch_step(const fk_batch* b, int from, hipStream_t s)
 }
 
 template <int TI>
-hipError_t batch_occupancy_t(int k, size_t lds, int* occ)
+hipError_t batch_occupancy_t(int k, int nt, size_t lds, int* occ)
 {
-    const int nt = class_threads(k);
     switch (class_body(k)) {
     case BODY_FAST: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_batch_sweep<TI, BODY_FAST>, nt, lds);
     case BODY_REST: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_batch_sweep<TI, BODY_REST>, nt, lds);
@@ -1244,9 +1247,9 @@ hipError_t batch_occupancy_t(int k, size_t lds, int* occ)
     }
 }
 
-int batch_occupancy(int ti, int k, size_t lds, int* occ)
+int batch_occupancy(int ti, int k, int nt, size_t lds, int* occ)
 {
-    const hipError_t e = ti == 4 ? batch_occupancy_t<4>(k, lds, occ) : batch_occupancy_t<8>(k, lds, occ);
+    const hipError_t e = ti == 4 ? batch_occupancy_t<4>(k, nt, lds, occ) : batch_occupancy_t<8>(k, nt, lds, occ);
     return e == hipSuccess ? FK_OK : FK_E_HIP;
 }
 
@@ -1266,6 +1269,17 @@ int batch_build(fk_batch* b, int wgs_per_cu)
         if (b->active[m]) compact.push_back((int)m);
     b->n_active = (int)compact.size();
     if (b->n_active == 0) return FK_OK;
+    if (b->single) {
+        // width of the single launch's workgroups.  256 threads hold 4, 2 or
+        // 1 tiles of 64-, 128- or 256-lane v_y blocks (a wave idles beside a
+        // 192-lane block); 192 threads hold 3, 1 or 1 tiles of 64-, 128- or
+        // 192-lane blocks.  256 unless the caller (the autotuner) picked 192
+        // and every block fits: on 64 uneven instances, 82% of whose cells
+        // have 129-192 v_y lanes, 192 still ran 2% slower than 256.
+        int max_block = 0;
+        for (int m : compact) max_block = std::max(max_block, b->inst[m]->L.block);
+        b->single_threads = (b->single_width == 192 && max_block <= 192) ? 192 : 256;
+    }
     std::vector<BatchItem> cls[kBatchClasses];
     for (size_t q = 0; q < compact.size(); ++q) {
         fk_ctx* c = b->inst[compact[q]];
@@ -1274,7 +1288,7 @@ int batch_build(fk_batch* b, int wgs_per_cu)
         d.sw[1] = sweep_args<float>(c, 1);
         d.fd = field_args(c, 1);
         d.block = c->L.block;
-        d.group = std::min(kBatchMaxGroup, kBatchThreads / c->L.block);
+        d.group = b->single ? b->single_threads / c->L.block : std::min(kBatchMaxGroup, kBatchThreads / c->L.block);
         d.kc = c->L.kc;
         d.nx = c->p.nx;
         d.lds_doubles = (int)batch_slice_doubles(b->ti, c->L.block, c->L.kc);
@@ -1343,7 +1357,7 @@ int batch_build(fk_batch* b, int wgs_per_cu)
     for (int k = 0; k < kBatchClasses; ++k) {
         if (b->cls_n[k] == 0) continue;
         int occ = 0;
-        if (batch_occupancy(b->ti, k, b->lds, &occ))
+        if (batch_occupancy(b->ti, k, batch_threads(b, k), b->lds, &occ))
             return set_error(&b->err, FK_E_HIP, "hipOccupancyMaxActiveBlocksPerMultiprocessor failed");
         if (occ < 1) return set_error(&b->err, FK_E_INVALID, "batch tiles need more LDS than a compute unit has");
         // the fast classes carry the bulk: they take the tuned occupancy
@@ -1436,11 +1450,12 @@ extern "C" int fk_batch_create(const fk_params* params, int n, void* stream, int
     fk_batch* b = new (std::nothrow) fk_batch();
     if (!b) return set_error(nullptr, FK_E_OOM, "host allocation failed");
     b->stream = static_cast<hipStream_t>(stream);
-    if (mode < 0 || mode > 2) {
+    if (mode < 0 || mode > 3) {
         delete b;
-        return set_error(nullptr, FK_E_INVALID, "batch mode must be 0, 1 or 2");
+        return set_error(nullptr, FK_E_INVALID, "batch mode must be 0, 1, 2 or 3");
     }
-    b->single = mode == 2 ? 1 : 0;
+    b->single = mode >= 2 ? 1 : 0;
+    b->single_width = mode == 3 ? 192 : 0;
     int rc = FK_OK;
     hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) rc = bfail(b, e, "hipStreamCreateWithFlags");
@@ -1461,7 +1476,7 @@ extern "C" int fk_batch_create(const fk_params* params, int n, void* stream, int
         // short run, then start the instances again from f = 0
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = FK_E_HIP;
-        int best_ti = 8, best_kc = 32, best_occ = 0, best_sched = 0, best_single = 0;
+        int best_ti = 8, best_kc = 32, best_occ = 0, best_sched = 0, best_single = 0, best_width = 0;
         float best_ms = 1e30f;
         const int tis[2] = {4, 8};
         const int kcs[3] = {16, 32, 64};
@@ -1470,11 +1485,13 @@ extern "C" int fk_batch_create(const fk_params* params, int n, void* stream, int
             for (int kc : kcs)
                 for (int occ : occs)
                 for (int sched = 0; sched < 2; ++sched)
-                for (int single = 0; single < 2; ++single) {
+                for (int variant = 0; variant < 3; ++variant) {   // split; single at 256 or 192 threads
                     if (rc) break;
+                    const int single = variant > 0 ? 1 : 0;
                     b->ti = ti;
                     b->sched = sched;
                     b->single = single;
+                    b->single_width = variant == 1 ? 256 : (variant == 2 ? 192 : 0);
                     for (auto c : b->inst) {
                         const int kcc = std::min(kc, c->p.nx);
                         if (!rc) rc = retile(c, ti, kcc < 4 ? 0 : kcc);
@@ -1495,6 +1512,7 @@ extern "C" int fk_batch_create(const fk_params* params, int n, void* stream, int
                         best_occ = occ;
                         best_sched = sched;
                         best_single = single;
+                        best_width = b->single_width;
                     }
                 }
         if (e0) (void)hipEventDestroy(e0);
@@ -1503,6 +1521,7 @@ extern "C" int fk_batch_create(const fk_params* params, int n, void* stream, int
             b->ti = best_ti;
             b->sched = best_sched;
             b->single = best_single;
+            b->single_width = best_width;
             for (auto c : b->inst) {
                 const int kcc = std::min(best_kc, c->p.nx);
                 if (!rc) rc = retile(c, best_ti, kcc < 4 ? 0 : kcc);
@@ -1578,6 +1597,7 @@ extern "C" int fk_batch_info(const fk_batch* b, fk_batch_info_t* out)
     int launches = 0;
     for (int k = 0; k < kBatchClasses; ++k) launches += b->cls_n[k] > 0;
     out->sweep_launches = launches;
+    out->single_threads = b->single ? b->single_threads : 0;
     return FK_OK;
 }
 

@@ -77,7 +77,7 @@ class fk_batch_info_t(C.Structure):
     _fields_ = [
         ("n", C.c_int32), ("tile_rows", C.c_int32), ("tile_planes", C.c_int32),
         ("grid", C.c_int32), ("items", C.c_int32), ("lds_bytes", C.c_int64), ("cells", C.c_int64),
-        ("schedule", C.c_int32), ("sweep_launches", C.c_int32),
+        ("schedule", C.c_int32), ("sweep_launches", C.c_int32), ("single_threads", C.c_int32),
     ]
 
     def as_dict(self):
@@ -323,13 +323,14 @@ class Batch:
     (fk_batch_*): one sweep launch per step by default, split launches with
     ``single_launch=False``, or whatever ``autotune`` finds fastest."""
 
-    def __init__(self, cfgs, stream=None, autotune=False, trace_stride=1, single_launch=True, **kw):
+    def __init__(self, cfgs, stream=None, autotune=False, trace_stride=1, single_launch=True, single_threads=256,
+                 **kw):
         self.cfgs = list(cfgs)
         strides = trace_stride if isinstance(trace_stride, (list, tuple)) else [trace_stride] * len(self.cfgs)
         arr = (fk_params * len(self.cfgs))(*[make_params(c, "f32", trace_stride=st, **kw)
                                              for c, st in zip(self.cfgs, strides)])
         h = _vp()
-        mode = 1 if autotune else (2 if single_launch else 0)
+        mode = 1 if autotune else ((3 if single_threads == 192 else 2) if single_launch else 0)
         rc = fk_batch_create(arr, len(self.cfgs), stream, mode, C.byref(h))
         if rc != OK:
             raise FlashkinError(rc, (fk_batch_last_error(None) or b"").decode())

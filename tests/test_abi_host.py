@@ -105,7 +105,7 @@ def test_saturation_check():
 
 
 def test_batch_rejects_before_touching_the_gpu():
-    """Batched instances are FP32 with nvy <= 256 and the mode is 0, 1 or 2;
+    """Batched instances are FP32 with nvy <= 256 and the mode is 0 .. 3;
     these are checked on the host before any device call."""
     good = W.config(nx=16, nvx=16, nvy=64, length=1e-3, ey=-5e6, delta_max=2.5, a_max_ev=400.0)
     wide = dict(good, nvy=300)
@@ -117,4 +117,5 @@ def test_batch_rejects_before_touching_the_gpu():
         assert fk.fk_batch_last_error(None)
     arr = (fk.fk_params * 1)(fk.make_params(good, "f32"))
     assert fk.fk_batch_create(arr, 0, None, 0, C.byref(C.c_void_p())) == fk.E_INVALID
-    assert fk.fk_batch_create(arr, 1, None, 3, C.byref(C.c_void_p())) == fk.E_INVALID
+    assert fk.fk_batch_create(arr, 1, None, 4, C.byref(C.c_void_p())) == fk.E_INVALID
+    assert fk.fk_batch_create(arr, 1, None, -1, C.byref(C.c_void_p())) == fk.E_INVALID

@@ -70,14 +70,17 @@ def test_batch_members_match_oracle(fk, autotune):
             assert abs(s - orc["sigma"]) <= 1e-5 * abs(orc["sigma"]) + 1e-30, m
 
 
-@pytest.mark.parametrize("single", [False, True])
-def test_batch_is_bitwise_a_standalone_context(fk, single):
-    """Split launches and one sweep launch per step give the same bits as
-    single contexts with the same tiling."""
-    cfgs = small_instances(9, 5)
-    with fk.Batch(cfgs, tile_planes=16, single_launch=single) as b:
+@pytest.mark.parametrize("single,threads", [(False, 256), (True, 256), (True, 192)])
+def test_batch_is_bitwise_a_standalone_context(fk, single, threads):
+    """Split launches and one sweep launch per step (in workgroups of 256 or
+    192 threads) give the same bits as single contexts with the same
+    tiling."""
+    cfgs = [c for c in small_instances(9, 8) if c["nvy"] <= 192][:5]
+    assert len(cfgs) == 5 and len({-(-c["nvy"] // 64) for c in cfgs}) >= 2
+    with fk.Batch(cfgs, tile_planes=16, single_launch=single, single_threads=threads) as b:
         info = b.info()
         assert (info["sweep_launches"] == 1) == single
+        assert info["single_threads"] == (threads if single else 0)
         b.step(45)
         b.sync()
         outs = [(v.f(), v.state()) for v in b.views]
