@@ -70,14 +70,15 @@ struct GemmPair {
 // v_mfma_f32_32x32x16_bf16, splitting K: wave w takes the K steps
 // w, w + 4, w + 8, ... (16 each), so each wave's chain of dependent loads is
 // a quarter of K; the four partial tiles are summed through LDS (fixed
-// order) and wave 0 runs the epilogue.  Lane l holds A[row l%32][k0 + 8(l/32)
+// order), each wave finishing a quarter of the tile's elements and running
+// their epilogue.  Lane l holds A[row l%32][k0 + 8(l/32)
 // .. +7] and B[col l%32][same k] and accumulates C element e at row
 // 8(e/4) + 4(l/32) + e%4, column l%32 of the tile.
 constexpr int kGemmTile = 32;
 
 __global__ void __launch_bounds__(256) k_gemm_nt(GemmPair gp)
 {
-    __shared__ float part[3][16][64];       // waves 1..3: [element][lane]
+    __shared__ float part[4][16][64];       // every wave's partial tile: [wave][element][lane]
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int second = (int)blockIdx.x >= gp.tiles0 ? 1 : 0;
     const GemmArgs& g = gp.p[second];
@@ -89,33 +90,58 @@ __global__ void __launch_bounds__(256) k_gemm_nt(GemmPair gp)
     const bool a_ok = ra < g.M, b_ok = rb < g.N;
     const __bf16* pa = g.A + (size_t)(a_ok ? ra : 0) * g.lda + kk;
     const __bf16* pb = g.B + (size_t)(b_ok ? rb : 0) * g.ldb + kk;
+    // After the reduction wave w finishes elements 4w .. 4w + 3 of every
+    // lane: rows m0 + 8w + 4 (lane / 32) + i, column n0 + lane % 32.  Their
+    // bias and pre-activation operands are loaded now, alongside the first
+    // operand group, not after the reduction.
+    const int col = n0 + (lane & 31);
+    const bool col_ok = col < g.N;
+    float bias_c = 0.0f, zpre[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (col_ok) {
+        if (g.epi == EPI_HIDDEN || g.epi == EPI_OUTPUT) bias_c = g.bias[col];
+        if (g.epi == EPI_DGRAD) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = m0 + 8 * w + 4 * (lane >> 5) + i;
+                zpre[i] = g.zin[(size_t)min(row, g.M - 1) * g.ldzin + col];
+            }
+        }
+    }
     f32x16 acc = {0};
     const bf16x8 zero = {0};
-#pragma unroll 8
-    for (int k0 = 16 * w; k0 < g.K; k0 += 64) {
-        const bf16x8 a = a_ok ? *reinterpret_cast<const bf16x8*>(pa + k0) : zero;
-        const bf16x8 b = b_ok ? *reinterpret_cast<const bf16x8*>(pb + k0) : zero;
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
-    }
-    if (w > 0) {
+    // The wave's K steps (every fourth of 16) in groups of 8: all 16 operand
+    // loads of a group are issued before its first MFMA, so a group costs one
+    // memory latency.  Loads are unconditional (rows outside the matrix read
+    // row 0, steps past the end repeat the last one) and the values are
+    // zeroed or skipped afterwards; the MFMAs run in K order.
+    const int nsteps = g.K > 16 * w ? (g.K - 16 * w + 63) / 64 : 0;
+    for (int s0 = 0; s0 < nsteps; s0 += 8) {
+        bf16x8 av[8], bv[8];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) part[w - 1][e][lane] = acc[e];
+        for (int u = 0; u < 8; ++u) {
+            const int k0 = 16 * w + 64 * min(s0 + u, nsteps - 1);
+            av[u] = *reinterpret_cast<const bf16x8*>(pa + k0);
+            bv[u] = *reinterpret_cast<const bf16x8*>(pb + k0);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (s0 + u < nsteps)
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_ok ? av[u] : zero, b_ok ? bv[u] : zero, acc, 0, 0, 0);
     }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) part[w][e][lane] = acc[e];
     __syncthreads();
-    if (w > 0) return;
+    if (!col_ok) return;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc[e] = ((acc[e] + part[0][e][lane]) + part[1][e][lane]) + part[2][e][lane];
-    const int col = n0 + (lane & 31);
-    if (col >= g.N) return;
-    const float bcol = (g.epi == EPI_HIDDEN || g.epi == EPI_OUTPUT) ? g.bias[col] : 0.0f;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const int row = m0 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+    for (int i = 0; i < 4; ++i) {
+        const int e = 4 * w + i;
+        const int row = m0 + 8 * w + 4 * (lane >> 5) + i;
         if (row >= g.M) continue;
-        const float v = acc[e];
+        // the four waves' partial sums, added in wave order
+        const float v = ((part[0][e][lane] + part[1][e][lane]) + part[2][e][lane]) + part[3][e][lane];
         switch (g.epi) {
         case EPI_HIDDEN: {
-            const float z = v + bcol;
+            const float z = v + bias_c;
             g.out[(size_t)row * g.ldout + col] = z;
             const __bf16 h = (__bf16)gelu(z);
             g.act[(size_t)row * g.ldact + col] = h;
@@ -123,10 +149,10 @@ __global__ void __launch_bounds__(256) k_gemm_nt(GemmPair gp)
             break;
         }
         case EPI_OUTPUT:
-            g.out[(size_t)row * g.ldout + col] = v + bcol;
+            g.out[(size_t)row * g.ldout + col] = v + bias_c;
             break;
         case EPI_DGRAD: {
-            const __bf16 d = (__bf16)(v * gelu_grad(g.zin[(size_t)row * g.ldzin + col]));
+            const __bf16 d = (__bf16)(v * gelu_grad(zpre[i]));
             g.act[(size_t)row * g.ldact + col] = d;
             g.actT[(size_t)col * g.ldactT + row] = d;
             break;
