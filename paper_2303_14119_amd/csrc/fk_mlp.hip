@@ -281,13 +281,8 @@ struct AdamArgs {
     float lr, b1, b2, eps, c1, c2;   // c1 = 1 - b1^t, c2 = 1 - b2^t
 };
 
-__global__ void __launch_bounds__(256) k_adamw(AdamArgs a)
+__device__ __forceinline__ float adamw_update(const AdamArgs& a, const AdamSeg& q, int idx)
 {
-    int s = 0;
-    while (s + 1 < a.nseg && (int)blockIdx.x >= a.first[s + 1]) ++s;
-    const AdamSeg& q = a.seg[s];
-    const int idx = ((int)blockIdx.x - a.first[s]) * blockDim.x + threadIdx.x;
-    if (idx >= q.count) return;
     const float g = q.g[idx];
     const float m = a.b1 * q.m[idx] + (1.0f - a.b1) * g;
     const float v = a.b2 * q.v[idx] + (1.0f - a.b2) * g * g;
@@ -297,10 +292,48 @@ __global__ void __launch_bounds__(256) k_adamw(AdamArgs a)
     float w = q.w[idx];
     w -= a.lr * (mh / (sqrtf(vh) + a.eps) + q.wd * w);
     q.w[idx] = w;
-    if (q.wbf) {
-        const int r = idx / q.ld, c = idx % q.ld;
-        q.wbf[idx] = (__bf16)w;
-        q.wtbf[(size_t)c * q.ldT + r] = (__bf16)w;
+    return w;
+}
+
+// A weight segment is covered by 32 x 32 tiles, one per workgroup: the
+// update and the row-major bf16 copy go out along rows, and the transposed
+// copy is staged through LDS so that it too is written in runs of
+// consecutive addresses.  A bias segment is a plain range of 256 per
+// workgroup.
+__global__ void __launch_bounds__(256) k_adamw(AdamArgs a)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 tile_t[32][36];   // [column][row]; rows 8-byte aligned
+    int s = 0;
+    while (s + 1 < a.nseg && (int)blockIdx.x >= a.first[s + 1]) ++s;
+    const AdamSeg& q = a.seg[s];
+    const int blk = (int)blockIdx.x - a.first[s];
+    if (!q.wbf) {
+        const int idx = blk * blockDim.x + threadIdx.x;
+        if (idx < q.count) adamw_update(a, q, idx);
+        return;
+    }
+    const int rows = q.count / q.ld;
+    const int ntc = (q.ld + 31) / 32;
+    const int r0 = (blk / ntc) * 32, c0 = (blk % ntc) * 32;
+    const int cc = threadIdx.x & 31, rg = threadIdx.x >> 5;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int rr = rg + 8 * i, r = r0 + rr, c = c0 + cc;
+        __bf16 h = (__bf16)0.0f;
+        if (r < rows && c < q.ld) {
+            const int idx = r * q.ld + c;
+            h = (__bf16)adamw_update(a, q, idx);
+            q.wbf[idx] = h;
+        }
+        tile_t[cc][rr] = h;
+    }
+    __syncthreads();
+    // transposed copy: thread -> column c0 + t / 8, rows r0 + 4 (t % 8) .. + 3
+    const int c = c0 + (threadIdx.x >> 3), rq = 4 * (threadIdx.x & 7);
+    if (c < q.ld && r0 + rq < rows) {
+        typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+        const u32x2 v = *reinterpret_cast<const u32x2*>(&tile_t[threadIdx.x >> 3][rq]);
+        *reinterpret_cast<u32x2*>(q.wtbf + (size_t)c * q.ldT + r0 + rq) = v;
     }
 }
 
@@ -632,7 +665,7 @@ extern "C" int fk_mlp_adamw(fk_mlp* n, double lr, double beta1, double beta2, do
         w.count = n->pad[l + 1] * n->pad[l];
         w.wd = (float)weight_decay;
         a.first[a.nseg++] = blocks;
-        blocks += (w.count + 255) / 256;
+        blocks += (n->pad[l + 1] / 32) * ((n->pad[l] + 31) / 32);   // 32 x 32 tiles
         AdamSeg& b = a.seg[a.nseg];   // bias: no weight decay, no bf16 copies
         b.w = n->b[l];
         b.g = n->gb[l];
