@@ -32,12 +32,16 @@ PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "sweep_c1_rocprof.md")
 
 
 def kernel_source_digest():
-    """Hash of the sweep kernel's device code and of the layout rules that
-    shape its launch (tile rows, planes, workgroup size)."""
+    """Hash of the sweep kernel's device code and of the code that shapes
+    its launch (tile rows, planes, workgroup size), comments and whitespace
+    left out."""
     h = hashlib.sha256()
-    for name in ("fk_internal.h", "fk_kernels.h", "fk_sweep_fast.h", "fk_host.cpp"):
-        with open(os.path.join(ROOT, "paper_2303_14119_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
+    for name in ("fk_internal.h", "fk_kernels.h", "fk_sweep_fast.h", "fk_host.cpp", "fk_solver.hip"):
+        with open(os.path.join(ROOT, "paper_2303_14119_amd", "csrc", name), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -13,7 +13,10 @@
 // Per row the thread keeps the two x planes the upwind update reads plus
 // one prefetched plane.  Rows outside the grid (the halo below the first
 // tile, above the last) and lanes past nvy read 0 and store nothing through
-// the buffer range check, so the body has no per-row lane masks.
+// the buffer range check, so the body has no per-row lane masks.  Inside
+// the plane loop the only memory operations are the next plane's loads and
+// this plane's stores (the per-plane coefficients sit in LDS), so the
+// prefetch stays in flight while the plane is computed.
 #pragma once
 
 #include "fk_kernels.h"
