@@ -95,7 +95,7 @@ typedef struct {
     double ex_external;      /* uniform E_x added to the self field, V/m */
     int32_t trace_stride;    /* record observables every trace_stride steps (>= 1) */
     int32_t trace_cap;       /* records held on the device between drains (>= 1) */
-    int32_t tile_rows;       /* v_x rows per tile, 0 = library choice */
+    int32_t tile_rows;       /* v_x rows per tile: 4, 8, 12 or 16 (12 and 16: FK_F32, nvy <= 512), 0 = library choice */
     int32_t tile_planes;     /* x planes per tile; 0: chosen at creation from the sweep kernel's occupancy: the longest run (16..128) that keeps 8 waves resident per compute unit, or all a unit holds, with the workgroups spread evenly (fk_validate reports a host-side estimate, fk_query the choice); batch instances get 16 */
 } fk_params;
 
@@ -233,7 +233,7 @@ int fk_kernel_times(fk_ctx* ctx, double* sweep_ms, int64_t* sweep_count, double*
 
 /* Tiling autotuner (a project addition; the paper prescribes no kernel
  * layout).  Times trial_steps >= 2 steps for each candidate tiling (v_x rows
- * 4/8/16 x x planes 16/32/64/128 that fit) and keeps the fastest.  The state
+ * 4/8/12/16 x x planes 16/32/64/128 that fit) and keeps the fastest.  The state
  * (f, sigma, step, trace history) is the same afterwards.  The chosen layout
  * is written to *chosen if it is not NULL. */
 int fk_autotune(fk_ctx* ctx, int trial_steps, fk_info* chosen);

@@ -45,8 +45,8 @@ int derive_layout(const fk_params* p, Layout* L, std::string* why)
     if (p->emission_norm != FK_EMIT_DISCRETE && p->emission_norm != FK_EMIT_ANALYTIC) return bad("bad emission_norm");
     if (p->physics_mask & ~(uint32_t)FK_PHYS_ALL) return bad("unknown physics_mask bits");
     if (p->trace_stride < 1 || p->trace_cap < 1) return bad("trace_stride and trace_cap must be >= 1");
-    if (p->tile_rows != 0 && p->tile_rows != 4 && p->tile_rows != 8 && p->tile_rows != 16)
-        return bad("tile_rows must be 0, 4, 8 or 16");
+    if (p->tile_rows != 0 && p->tile_rows != 4 && p->tile_rows != 8 && p->tile_rows != 12 && p->tile_rows != 16)
+        return bad("tile_rows must be 0, 4, 8, 12 or 16");
     if (p->tile_planes != 0 && (p->tile_planes < 4 || p->tile_planes > 128))
         return bad("tile_planes must be 0 or in [4, 128]");
 
@@ -87,14 +87,20 @@ int derive_layout(const fk_params* p, Layout* L, std::string* why)
         // FP32: 8 rows keep the fast body at four waves per SIMD, best up to
         // 256 v_y lanes; from 320 lanes (5+ waves per workgroup) 16 rows
         // halve the per-plane barrier, exchange and reduction work per row
-        // and win (measured 8-12%) as long as the tile fits in LDS.
+        // and win (measured 8-12%) as long as the tile fits in LDS.  12 rows
+        // fit 3 waves per SIMD (16 rows: 2), so two 6-wave workgroups share
+        // a unit; they win (3-4% at 384 lanes) when every 12-row tile is
+        // full and meets the v_x sign change at its edge (nvx a multiple of
+        // 24); otherwise the generic body on split tiles costs more.
         // FP64: 4 rows.
         ti = l.elem == 4 ? 8 : 4;
         if (l.elem == 4 && l.block >= 320 && l.block <= 512 && sweep_lds(16, l.block, 16, l.elem) <= kLdsBudget)
             ti = 16;
+        if (ti == 16 && p->nvx % 24 == 0 && sweep_lds(12, l.block, 16, l.elem) <= kLdsBudget) ti = 12;
         while (ti > 4 && sweep_lds(ti, l.block, 16, l.elem) > kLdsBudget) ti /= 2;
     }
     if (ti == 16 && (l.elem != 4 || l.block > 512)) return bad("tile_rows 16 needs FK_F32 and nvy <= 512");
+    if (ti == 12 && (l.elem != 4 || l.block > 512)) return bad("tile_rows 12 needs FK_F32 and nvy <= 512");
     if (ti == 8 && l.elem == 8 && l.block > 512) return bad("tile_rows 8 with FK_F64 needs nvy <= 512");
     l.ti = ti;
     l.n_it = (p->nvx + ti - 1) / ti;

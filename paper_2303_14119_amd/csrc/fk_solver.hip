@@ -311,6 +311,7 @@ void launch_sweep(const fk_ctx* c, int from, hipStream_t s)
     if (c->L.elem == 4) {
         switch (c->L.ti) {
         case 16: launch_sweep_t<float, 16, 512>(c, from, s); break;
+        case 12: launch_sweep_t<float, 12, 512>(c, from, s); break;
         case 8: small ? launch_sweep_t<float, 8, 512>(c, from, s) : launch_sweep_t<float, 8, 1024>(c, from, s); break;
         default: launch_sweep_t<float, 4, 1024>(c, from, s); break;
         }
@@ -328,6 +329,7 @@ void launch_moments(const fk_ctx* c, hipStream_t s)
         auto a = sweep_args<float>(c, c->cur);
         switch (c->L.ti) {
         case 16: hipLaunchKernelGGL((k_moments<float, 16>), dim3(c->L.nwg), dim3(c->L.block), c->L.lds_moments, s, a); break;
+        case 12: hipLaunchKernelGGL((k_moments<float, 12>), dim3(c->L.nwg), dim3(c->L.block), c->L.lds_moments, s, a); break;
         case 8: hipLaunchKernelGGL((k_moments<float, 8>), dim3(c->L.nwg), dim3(c->L.block), c->L.lds_moments, s, a); break;
         default: hipLaunchKernelGGL((k_moments<float, 4>), dim3(c->L.nwg), dim3(c->L.block), c->L.lds_moments, s, a); break;
         }
@@ -643,7 +645,7 @@ int retile(fk_ctx* c, int ti, int kc)
 std::vector<std::pair<int, int>> tile_candidates(const fk_params& p)
 {
     std::vector<std::pair<int, int>> out;
-    const int tis[3] = {4, 8, 16};
+    const int tis[4] = {4, 8, 12, 16};
     const int kcs[4] = {16, 32, 64, 128};
     for (int ti : tis)
         for (int kc : kcs) {
@@ -666,6 +668,8 @@ int sweep_wgs_per_cu(const Layout& L)
     if (L.elem == 4) {
         if (L.ti == 16)
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sweep<float, 16, 512>, L.block, L.lds_sweep);
+        else if (L.ti == 12)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sweep<float, 12, 512>, L.block, L.lds_sweep);
         else if (L.ti == 8)
             e = small ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sweep<float, 8, 512>, L.block, L.lds_sweep)
                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sweep<float, 8, 1024>, L.block, L.lds_sweep);

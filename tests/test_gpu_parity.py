@@ -139,6 +139,37 @@ def test_ragged_random_state(fk, case, dtype):
         compare_state(s.state(), o.record(), tol_s)
 
 
+TALL = [
+    # (tile_rows, nx, nvx, nvy): every tile at an edge split; ragged last
+    # tile; a tile split inside (generic body); 320..512-lane blocks
+    (12, 23, 48, 100),
+    (12, 17, 41, 330),
+    (12, 11, 30, 512),
+    (16, 19, 40, 200),
+    (16, 13, 45, 384),
+]
+
+
+@pytest.mark.parametrize("case", TALL, ids=[f"ti{c[0]}-{c[1]}x{c[2]}x{c[3]}" for c in TALL])
+def test_tall_tiles_random_state(fk, case):
+    """FP32 runs with 12- and 16-row tiles (the layouts for wide v_y blocks)
+    against the oracle, whatever the library would pick for the shape."""
+    ti, nx, nvx, nvy = case
+    cfg = W.config(nx=nx, nvx=nvx, nvy=nvy, length=nx * 2e-6, ey=-4e6, delta_max=2.5, a_max_ev=400.0,
+                   x_src_lo=1e-6, x_src_hi=5e-6, j_src=1e7, cfl=0.8)
+    f0 = W.random_state((nx, nvx, nvy), seed=ti * 100 + nvy, scale=1e3).astype(np.float32).astype(np.float64)
+    o = Oracle(cfg)
+    o.set_state(f0, 3e-6, 0)
+    with fk.Solver(cfg, "f32", tile_rows=ti) as s:
+        assert s.info["tile_rows"] == ti
+        s.write_state(f0, 3e-6, 0.0, 0)
+        o.step(25)
+        s.step(25)
+        s.sync()
+        assert rel_l2(s.f(), o.f()) <= 1e-5
+        compare_state(s.state(), o.record(), 1e-5)
+
+
 def test_particle_balance_fp64(fk):
     cfg = W.c0()
     with fk.Solver(cfg, "f64", trace_cap=1024) as s:
