@@ -76,6 +76,25 @@ def test_width_limits_per_precision():
         assert fk.fk_validate(C.byref(p), None) == code, (nvy, dtype)
 
 
+def test_tile_rows_rule_and_limits():
+    """The library's tile height (host rule): 8 rows up to 256 FP32 lanes,
+    12 for 320-512 lanes when N_vx is a multiple of 24, else 16; 4 in FP64.
+    12 and 16 rows are FP32 only and need N_vy <= 512."""
+    def rows(nvx, nvy, dtype="f32", ti=0):
+        cfg = W.config(nx=64, nvx=nvx, nvy=nvy, length=1e-4, ey=-4e6, delta_max=2.5, a_max_ev=400.0, cfl=0.8)
+        p = fk.make_params(cfg, dtype, tile_rows=ti)
+        rc = fk.fk_validate(C.byref(p), None)
+        return fk.validate(p)["tile_rows"] if rc == fk.OK else rc
+    assert rows(256, 256) == 8
+    assert rows(384, 384) == 12 and rows(96, 400) == 12
+    assert rows(448, 448) == 16 and rows(320, 320) == 16 and rows(100, 384) == 16
+    assert rows(384, 384, "f64") == 4
+    assert rows(48, 200, ti=12) == 12
+    assert rows(48, 200, "f64", ti=12) == fk.E_INVALID
+    assert rows(48, 600, ti=12) == fk.E_INVALID and rows(48, 600, ti=16) == fk.E_INVALID
+    assert rows(48, 200, ti=6) == fk.E_INVALID
+
+
 def test_struct_size_and_version_are_checked():
     p = fk.make_params(W.c0())
     p.struct_size -= 8
