@@ -158,7 +158,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--batch-default", action="store_true",
                     help="batch mode: the default tiling and launch mode instead of the autotuned choice")
-    ap.add_argument("--sample-every", type=int, default=4,
+    ap.add_argument("--sample-every", type=int, default=16,
                     help="HIP events around every n-th step's kernels in the timed region")
     ap.add_argument("--pre-steps", type=int, default=3000,
                     help="steps run before the warmup to drive the state into the avalanche")
