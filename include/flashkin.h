@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define FK_ABI_VERSION 1u
+#define FK_ABI_VERSION 2u   /* 2: fk_batch_info_t gained single_threads */
 
 /* element type of f */
 enum { FK_F32 = 0, FK_F64 = 1 };

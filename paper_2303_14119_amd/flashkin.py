@@ -27,7 +27,7 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2303_14119_amd.build`")
 _lib = C.CDLL(LIB_PATH)
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 F32, F64 = 0, 1
 EMIT_DISCRETE, EMIT_ANALYTIC = 0, 1
 PHYS_X, PHYS_VX, PHYS_VY, PHYS_SRC, PHYS_SEE, PHYS_SELF_FIELD, PHYS_ALL = 1, 2, 4, 8, 16, 32, 63

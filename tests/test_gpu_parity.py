@@ -227,4 +227,6 @@ def test_profiled_steps_time_every_sweep_and_change_nothing(fk):
                 assert kt["sweep_n"] == want and kt["field_n"] == want
                 assert kt["sweep_ms"] > 0 and kt["field_ms"] > 0
             out.append(s.f())
+            with pytest.raises(fk.FlashkinError):
+                s.set_profiling(True, every=-1)
     assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
