@@ -1079,11 +1079,12 @@ namespace fk {
 
 constexpr int kBatchThreads = 256;
 constexpr int kBatchMaxGroup = kBatchThreads / 64;
-// Work classes, one sweep launch each.  Split mode (the default) uses four:
+// Work classes, one sweep launch each.  Split mode (mode 0) uses four:
 // main-body or other tiles, workgroups of 256 threads (v_y blocks of 64,
 // 128 or 256 lanes: 4, 2 or 1 tiles side by side) or of 192 threads (one
-// tile of a 192-lane block, no idle wave).  Single mode puts every tile in
-// class 4: one launch per step, each tile taking its body at run time.
+// tile of a 192-lane block, no idle wave).  Single mode (modes 2 and 3)
+// puts every tile in class 4: one launch per step in workgroups of 256 or
+// 192 threads, each tile taking its body at run time.
 constexpr int kBatchClasses = 5;
 enum BatchBody { BODY_FAST = 0, BODY_REST = 1, BODY_ANY = 2 };
 __host__ __device__ constexpr int class_body(int k) { return k < 2 ? BODY_FAST : (k < 4 ? BODY_REST : BODY_ANY); }
