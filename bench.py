@@ -133,20 +133,23 @@ def bench_mlp(args):
     for _ in range(args.warmup):
         step += 1
         net.forward(x.data_ptr(), m)
-        net.backward(t.data_ptr(), m)
+        net.backward(t.data_ptr(), m, read_loss=False)
         net.adamw(step)
+    net.take_loss()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    # the loss of every step is summed on the device and read once at the end
     for _ in range(args.steps):
         step += 1
         net.forward(x.data_ptr(), m)
-        net.backward(t.data_ptr(), m)
+        net.backward(t.data_ptr(), m, read_loss=False)
         net.adamw(step)
-    torch.cuda.synchronize()
+    mean_loss, _ = net.take_loss()
     el = time.perf_counter() - t0
     net.close()
     print(json.dumps({"mode": "mlp", "ms_per_step": round(el * 1e3 / args.steps, 4), "steps": args.steps,
                       "gflop_per_step": round(flops / 1e9, 4), "tflops": round(flops * args.steps / el / 1e12, 3),
+                      "mean_loss": mean_loss,
                       "mfma_bf16_peak_tflops": 2500.0}), flush=True)
 
 

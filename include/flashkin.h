@@ -324,8 +324,15 @@ int fk_mlp_forward(fk_mlp* net, const float* x, int M, float* y);
 
 /* Mean-squared-error loss against target (device FP32 [M][dims[n_layers]])
  * for the batch of the last forward (M a multiple of 16); computes every
- * parameter gradient.  *loss (host, may be NULL) receives the loss. */
+ * parameter gradient.  *loss (host, may be NULL) receives the loss, which
+ * synchronises the stream; with NULL the call only queues work.  Either
+ * way the loss is added to a device-side running sum (fk_mlp_take_loss). */
 int fk_mlp_backward(fk_mlp* net, const float* target, int M, float* loss);
+
+/* Synchronises; *mean (may be NULL) receives the mean of the losses of the
+ * fk_mlp_backward calls since the last take (0 if none) and *count (may be
+ * NULL) their number; the running sum starts again from zero. */
+int fk_mlp_take_loss(fk_mlp* net, double* mean, int64_t* count);
 
 /* One AdamW step (decoupled weight decay on the weights, none on biases)
  * with bias-corrected moments; step counts from 1. */

@@ -219,15 +219,21 @@ __global__ void __launch_bounds__(256) k_mlp_loss(const float* __restrict__ y, i
     if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
-// loss = scale * sum of the partials, in a fixed order (one workgroup)
+// loss = scale * sum of the partials, in a fixed order (one workgroup); the
+// loss is also added to the running sum acc[0] and acc[1] counts the steps
 __global__ void __launch_bounds__(256) k_mlp_loss_sum(const double* __restrict__ part, int n, double scale,
-                                                      float* __restrict__ loss)
+                                                      float* __restrict__ loss, double* __restrict__ acc_sum)
 {
     __shared__ double sh[256];
     double acc = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) acc += part[i];
     acc = mlp_block_sum(acc, sh);
-    if (threadIdx.x == 0) *loss = (float)(acc * scale);
+    if (threadIdx.x == 0) {
+        const float l = (float)(acc * scale);
+        *loss = l;
+        acc_sum[0] += (double)l;
+        acc_sum[1] += 1.0;
+    }
 }
 
 // Bias gradients of every layer in one launch: db_l[n] = sum_m dz_l[m][n]
@@ -368,6 +374,7 @@ struct fk_mlp {
     __bf16 *dz[kMaxLayers + 1], *dzT[kMaxLayers + 1];
     float* loss = nullptr;
     double* loss_part = nullptr;         // per-workgroup sums of squares
+    double* loss_acc = nullptr;          // [2]: sum of the step losses since the last take, steps
     std::string err;
 };
 
@@ -444,6 +451,7 @@ extern "C" int fk_mlp_create(int n_layers, const int32_t* dims, int max_batch, v
         need((void**)&n->dz[l], M * n->pad[l] * 2); need((void**)&n->dzT[l], M * n->pad[l] * 2);
     }
     need((void**)&n->loss, 256);
+    need((void**)&n->loss_acc, 256);
     need((void**)&n->loss_part, ((M + kLossRows - 1) / kLossRows) * sizeof(double));
     for (auto& q : want) off += (q.second + 255) & ~size_t(255);
     if (hipMalloc(&n->pool, off) != hipSuccess) {
@@ -581,7 +589,7 @@ extern "C" int fk_mlp_backward(fk_mlp* n, const float* target, int M, float* los
     hipLaunchKernelGGL(k_mlp_loss, dim3(loss_blocks), dim3(256), 0, n->stream, n->z[L], n->pad[L], target, M,
                        n->dims[L], n->pad[L], n->dz[L], n->pad[L], n->dzT[L], mb, n->loss_part);
     hipLaunchKernelGGL(k_mlp_loss_sum, dim3(1), dim3(256), 0, n->stream, n->loss_part, loss_blocks,
-                       1.0 / ((double)M * n->dims[L]), n->loss);
+                       1.0 / ((double)M * n->dims[L]), n->loss, n->loss_acc);
     for (int l = L; l >= 1; --l) {
         // weight and bias gradients of layer l (1-based): dW = dZ_l^T A_{l-1}
         GemmArgs g{};
@@ -681,6 +689,18 @@ extern "C" int fk_mlp_adamw(fk_mlp* n, double lr, double beta1, double beta2, do
     a.first[a.nseg] = blocks;
     hipLaunchKernelGGL(k_adamw, dim3(blocks), dim3(256), 0, n->stream, a);
     FK_MHIP(n, hipGetLastError());
+    return FK_OK;
+}
+
+extern "C" int fk_mlp_take_loss(fk_mlp* n, double* mean, int64_t* count)
+{
+    if (!n) return FK_E_INVALID;
+    double acc[2] = {0.0, 0.0};
+    FK_MHIP(n, hipMemcpyAsync(acc, n->loss_acc, sizeof(acc), hipMemcpyDeviceToHost, n->stream));
+    FK_MHIP(n, hipMemsetAsync(n->loss_acc, 0, sizeof(acc), n->stream));
+    FK_MHIP(n, hipStreamSynchronize(n->stream));
+    if (mean) *mean = acc[1] > 0.0 ? acc[0] / acc[1] : 0.0;
+    if (count) *count = (int64_t)acc[1];
     return FK_OK;
 }
 

@@ -128,6 +128,7 @@ SIGNATURES = {
     "fk_mlp_forward": (C.c_int, [_vp, _vp, C.c_int, _vp]),
     "fk_mlp_backward": (C.c_int, [_vp, _vp, C.c_int, _P(C.c_float)]),
     "fk_mlp_adamw": (C.c_int, [_vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int64]),
+    "fk_mlp_take_loss": (C.c_int, [_vp, _P(C.c_double), _P(C.c_int64)]),
     "fk_mlp_sync": (C.c_int, [_vp]),
 }
 for _name, (_res, _args) in SIGNATURES.items():
@@ -427,10 +428,21 @@ class MLP:
     def forward(self, x_ptr, m, y_ptr=None):
         self._chk(fk_mlp_forward(self._h, x_ptr, int(m), y_ptr))
 
-    def backward(self, t_ptr, m):
+    def backward(self, t_ptr, m, read_loss=True):
+        """Gradients for the last forward; returns the loss (a stream
+        synchronisation) unless read_loss is False."""
+        if not read_loss:
+            self._chk(fk_mlp_backward(self._h, t_ptr, int(m), None))
+            return None
         loss = C.c_float()
         self._chk(fk_mlp_backward(self._h, t_ptr, int(m), C.byref(loss)))
         return loss.value
+
+    def take_loss(self):
+        """(mean loss, number of steps) since the last take."""
+        mean, count = C.c_double(), C.c_int64()
+        self._chk(fk_mlp_take_loss(self._h, C.byref(mean), C.byref(count)))
+        return mean.value, count.value
 
     def adamw(self, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=1e-4):
         self._chk(fk_mlp_adamw(self._h, lr, beta1, beta2, eps, weight_decay, int(step)))

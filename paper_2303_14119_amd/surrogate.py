@@ -181,20 +181,20 @@ class Surrogate:
         Y = np.ascontiguousarray(Y, dtype=np.float32)
         hist = []
         m = self.batch
+        self.net.take_loss()                   # start the device-side loss sum afresh
         for ep in range(epochs):
             order = rng.permutation(n)         # shuffled on the host, uploaded per epoch
             xs = torch.from_numpy(X[order]).cuda()
             ys = torch.from_numpy(Y[order]).cuda()
-            losses = []
             for lo in range(0, n - m + 1, m):
                 self.step += 1
                 # cosine decay of the learning rate over the run
                 frac = ep / max(1, epochs - 1)
                 lr_t = lr * (0.05 + 0.95 * 0.5 * (1 + math.cos(math.pi * frac)))
                 self.net.forward(xs[lo:lo + m].data_ptr(), m)
-                losses.append(self.net.backward(ys[lo:lo + m].data_ptr(), m))
+                self.net.backward(ys[lo:lo + m].data_ptr(), m, read_loss=False)   # no per-step sync
                 self.net.adamw(self.step, lr=lr_t, weight_decay=weight_decay)
-            rec = {"epoch": ep, "train": float(np.mean(losses))}
+            rec = {"epoch": ep, "train": self.net.take_loss()[0]}
             if Xval is not None and (ep % 20 == 19 or ep == epochs - 1):
                 rec["val"] = float(np.mean((self.predict(Xval) - Yval) ** 2))
             hist.append(rec)

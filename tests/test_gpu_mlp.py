@@ -126,4 +126,16 @@ def test_training_reduces_loss(env):
         net.adamw(step, lr=1e-3, weight_decay=1e-4)
     print("loss", losses[0], "->", losses[-1])
     assert losses[-1] < 0.1 * losses[0]
+    # the device-side running sum saw the same 300 losses
+    mean, count = net.take_loss()
+    assert count == 300 and mean == pytest.approx(float(np.mean(losses)), rel=1e-6)
+    # without reading the loss back, steps only queue work; the sum keeps them
+    for step in range(301, 305):
+        lo = (step - 1) % 4 * m
+        net.forward(xd[lo:lo + m].data_ptr(), m)
+        assert net.backward(td[lo:lo + m].data_ptr(), m, read_loss=False) is None
+        net.adamw(step, lr=1e-3, weight_decay=1e-4)
+    mean, count = net.take_loss()
+    assert count == 4 and 0.0 < mean < losses[0]
+    assert net.take_loss() == (0.0, 0)
     net.close()
