@@ -115,7 +115,7 @@ def bench_batch(args):
 
 def bench_mlp(args):
     """Surrogate training steps (forward, backward, AdamW) at batch 256 on
-    the 5-512-512-512-512-258 network."""
+    the 7-512-512-512-512-258 network."""
     import numpy as np
     import torch
     from paper_2303_14119_amd import flashkin as fk

@@ -2,7 +2,8 @@
 
 A project addition beyond the paper: the paper advances every run from an
 empty domain to saturation (Section 3).  Here a multilayer perceptron maps a
-run's parameters (|E_y|, delta_max, A_max, T_se, L) to its saturated
+run's parameters (|E_y|, delta_max, A_max, T_se, L) and its grid
+resolution (N_x, N_v) to its saturated
 x-resolved enclosed charge sigma_enc(x) on 256 points plus the primary and
 secondary fluxes; its prediction initialises a new run, which then continues
 to saturation.  The plain cold start stays the fallback and the judge of the
@@ -23,16 +24,30 @@ from . import flashkin as fk
 from . import workloads as W
 
 NPTS = 256
-DIMS = [5, 512, 512, 512, 512, NPTS + 2]
+DIMS = [7, 512, 512, 512, 512, NPTS + 2]
 EPS0 = 8.8541878128e-12
-FEATURE_RANGES = np.array([(1e6, 10e6), (1.5, 3.5), (250.0, 600.0), (1.0, 5.0), (0.5e-3, 5e-3)])
+# physical inputs: |E_y|, delta_max, A_max, T_se, L over the sweep's ranges;
+# grid inputs: 1/N_x and 1/N_v (cell sizes in units of the domain), over the
+# sweep's N_x 256..1024 and N_v 64..192, so a finer grid than the sweep's
+# lies just beyond -1 rather than far outside the box
+FEATURE_RANGES = np.array([(1e6, 10e6), (1.5, 3.5), (250.0, 600.0), (1.0, 5.0), (0.5e-3, 5e-3),
+                           (1 / 1024, 1 / 256), (1 / 192, 1 / 64)])
+
+
+def features_raw(ey, delta_max, a_max_ev, t_se_ev, length, nx, nv):
+    """Inputs scaled to [-1, 1] from the sweep's ranges (array arguments)."""
+    raw = np.stack([np.abs(ey), delta_max, a_max_ev, t_se_ev, length,
+                    1.0 / np.asarray(nx, dtype=np.float64), 1.0 / np.asarray(nv, dtype=np.float64)], axis=-1)
+    lo, hi = FEATURE_RANGES[:, 0], FEATURE_RANGES[:, 1]
+    return (2.0 * (raw - lo) / (hi - lo) - 1.0).astype(np.float32)
 
 
 def features(cfgs):
-    """Inputs scaled to [-1, 1] from the sweep's ranges."""
-    raw = np.array([[abs(c["ey"]), c["delta_max"], c["a_max_ev"], c["t_se_ev"], c["length"]] for c in cfgs])
-    lo, hi = FEATURE_RANGES[:, 0], FEATURE_RANGES[:, 1]
-    return (2.0 * (raw - lo) / (hi - lo) - 1.0).astype(np.float32)
+    """Network inputs of run dictionaries.  The velocity resolution is taken
+    from N_vx (the sweep draws N_vx = N_vy)."""
+    cols = np.array([[c["ey"], c["delta_max"], c["a_max_ev"], c["t_se_ev"], c["length"], c["nx"], c["nvx"]]
+                     for c in cfgs], dtype=np.float64).reshape(-1, 7)
+    return features_raw(*cols.T)
 
 
 def encode(profile, g_pe, g_see, ey):
@@ -257,15 +272,17 @@ def _raw(cfgs):
 
 def load_data(paths, saturated_only=True):
     """Concatenate generated .npz files; by default only the runs that
-    reached the Section 2 saturation test."""
-    xs, ys, raws = [], [], []
+    reached the Section 2 saturation test.  The inputs are rebuilt from the
+    stored raw parameters, so files written with another feature set load
+    the same way."""
+    ys, raws = [], []
     for p in paths:
         d = np.load(p)
-        keep = d["sat"].astype(bool) if saturated_only else np.ones(len(d["X"]), dtype=bool)
-        xs.append(d["X"][keep])
+        keep = d["sat"].astype(bool) if saturated_only else np.ones(len(d["Y"]), dtype=bool)
         ys.append(d["Y"][keep])
         raws.append(d["raw"][keep])
-    return np.concatenate(xs), np.concatenate(ys), np.concatenate(raws)
+    raw = np.concatenate(raws)
+    return features_raw(*raw[:, :7].T), np.concatenate(ys), raw
 
 
 def profile_errors(y_pred, y_true, raw):

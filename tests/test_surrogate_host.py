@@ -12,13 +12,34 @@ EPS0 = 8.8541878128e-12
 
 
 def test_features_map_the_sweep_box_to_unit_cube():
-    lo = W.config(nx=8, nvx=8, nvy=8, length=0.5e-3, ey=-1e6, delta_max=1.5, a_max_ev=250.0, t_se_ev=1.0)
-    hi = W.config(nx=8, nvx=8, nvy=8, length=5e-3, ey=-10e6, delta_max=3.5, a_max_ev=600.0, t_se_ev=5.0)
+    # the finest sweep grid has the smallest cells, so it sits at -1 with the
+    # smallest physical parameters
+    lo = W.config(nx=1024, nvx=192, nvy=192, length=0.5e-3, ey=-1e6, delta_max=1.5, a_max_ev=250.0, t_se_ev=1.0)
+    hi = W.config(nx=256, nvx=64, nvy=64, length=5e-3, ey=-10e6, delta_max=3.5, a_max_ev=600.0, t_se_ev=5.0)
     f = S.features([lo, hi])
+    assert f.shape == (2, S.DIMS[0])
     assert np.allclose(f[0], -1.0) and np.allclose(f[1], 1.0)
     # |E_y| is used, whatever the sign convention of the field
     mid = dict(lo, ey=+5.5e6)
     assert S.features([mid])[0][0] == pytest.approx(0.0, abs=1e-6)
+    # grid inputs are linear in the cell size: 1/512 is a third of the way
+    # from 1/1024 to 1/256, 1/96 halfway from 1/192 to 1/64
+    half = dict(lo, nx=512, nvx=96, nvy=96)
+    assert S.features([half])[0][5:] == pytest.approx([-1 / 3, 0.0], abs=1e-6)
+    # a grid four times finer than the sweep's coarsest x grid: 1/N_x = 1/1024
+    assert S.features([dict(lo, nx=4096)])[0][5] == pytest.approx(-1.5, abs=1e-6)
+
+
+def test_load_data_rebuilds_inputs_from_raw(tmp_path):
+    cfgs = W.c2_instances(seed=3, n=5)
+    raw = S._raw(cfgs)
+    y = np.zeros((5, S.NPTS + 2), dtype=np.float32)
+    sat = np.array([1, 0, 1, 1, 0])
+    # stored inputs of another width are ignored
+    np.savez(tmp_path / "d.npz", X=np.zeros((5, 3), np.float32), Y=y, sat=sat, raw=raw)
+    X, Y, r = S.load_data([str(tmp_path / "d.npz")])
+    keep = [c for c, s in zip(cfgs, sat) if s]
+    assert np.array_equal(X, S.features(keep)) and len(Y) == 3 and np.array_equal(r, raw[sat.astype(bool)])
 
 
 def test_encode_decode_round_trip():
