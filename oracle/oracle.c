@@ -18,17 +18,24 @@
  *     dielectric (Section 2, paragraph on the two velocity advections);
  *   - the SEE yield matrix (Eq 8-11), the primary and secondary wall fluxes
  *     (Eq 12-14), the half-Maxwellian emission boundary (Eq 15-16), the
- *     absorbing vacuum boundary (Eq 17) and the surface-charge update (Eq 18).
+ *     absorbing vacuum boundary (Eq 17) and the surface-charge update (Eq 18);
+ *   - optionally (ORC_BGK) the electron-electron collision term: relaxation
+ *     towards the Maxwellian of Eq 5 at T_e, at the frequency of Eq 4
+ *     (Eq 3), evaluated on f^n and n^n and added after the source.
  *
  * Readings taken where the paper is silent (all listed in the design notes):
  *   cell-centred grids; Lie splitting x, v_x, v_y, source; E_x^n from
  *   (n^n, sigma^n); fluxes from f^n; ghost row from Gamma_see^n; zero inflow
  *   and tallied outflow at the velocity-box edges; discrete normalisation of
- *   the emitted and source VDFs; source rate J_src as a parameter.
+ *   the emitted, source and collisional-equilibrium VDFs; source rate J_src
+ *   as a parameter; the collision term taken explicitly at f^n (so it
+ *   conserves each plane's density exactly) rather than after the sweeps.
  *
  * Parity is pinned by the CPU tests (binomial closed forms of upwind
  * transport, uniform-acceleration shift, linear field for uniform charge,
- * particle conservation, SEY identities, emission normalisation).
+ * particle conservation, SEY identities, emission normalisation; for the
+ * collision term the textbook electron collision time, the geometric
+ * relaxation of BGK alone and the temperature of its fixed point).
  */
 #include <math.h>
 #include <stdint.h>
@@ -52,6 +59,7 @@
 #define ORC_SRC   8u   /* field-emission band source, Eq 7 */
 #define ORC_SEE  16u   /* secondary emission, Eq 12-16 */
 #define ORC_SELF 32u   /* E_x from sigma and the electron charge */
+#define ORC_BGK  64u   /* electron-electron collisions, Eq 3-5 */
 
 typedef struct {
     int nx, nvx, nvy;
@@ -65,6 +73,8 @@ typedef struct {
     int emission_norm;      /* 0: discrete (emitted flux equals Gamma_see on the grid), 1: Eq 15 prefactor */
     unsigned physics_mask;
     double ex_external;     /* uniform E_x added to the self field, V/m */
+    double t_e_ev;          /* temperature of the collisional equilibrium (Eq 4-5), eV */
+    double ln_lambda;       /* Coulomb logarithm of Eq 4 */
 } orc_params;
 
 /* The observables of the state (f^n, sigma^n) after n steps. */
@@ -89,6 +99,8 @@ typedef struct {
     double *ghat;             /* nvx*nvy, unnormalised emission shape on v_x>0 cells */
     double zsum;              /* sum_{v_x>0} v_x ghat dvx dvy */
     double *fsrc;             /* nvx*nvy, source VDF, sum fsrc dvx dvy = 1 */
+    double *feq;              /* nvx*nvy, Eq 5 equilibrium at T_e, sum feq dvx dvy = 1 */
+    double *coll;             /* nx*nvx*nvy, collision increment of the step (ORC_BGK only) */
     double *wband;            /* nx, overlap of each cell with the band, fraction of dx */
     double *f, *g;            /* state and scratch, nx*nvx*nvy each */
     double *ne, *ex;          /* prologue: density and E_x of the current state */
@@ -97,6 +109,7 @@ typedef struct {
     int64_t step;
     double last_loss_v, last_resid;
     double cfl_max_vx;        /* largest |a_x| dt / dvx seen so far */
+    double nu_dt_max;         /* largest nu_ee dt seen so far (ORC_BGK) */
 } orc_sim;
 
 static size_t idx(const orc_sim* s, int k, int i, int j)
@@ -111,6 +124,15 @@ double orc_sey(double delta_max, double a_max_ev, double ks, double a_in_ev, dou
     if (z <= 0.0) return 0.0;
     return 1.526 * delta_max * (1.0 + ks * alpha * alpha / (2.0 * ORC_PI))
          * -expm1(-pow(z, 1.725)) / pow(z, 0.725);   /* 1 - exp(-z^1.725) */
+}
+
+/* ---- electron-electron collision frequency, Eq 4 ----------------------
+   n_e in 1/m^3, T_e in eV (converted to joules); the result is in 1/s. */
+double orc_nu_ee(double n_e, double t_e_ev, double ln_lambda)
+{
+    double te = t_e_ev * ORC_E;
+    return n_e * pow(ORC_E, 4) * ln_lambda
+         / (12.0 * pow(ORC_PI, 1.5) * ORC_EPS0 * ORC_EPS0 * sqrt(ORC_ME) * pow(te, 1.5));
 }
 
 static void build_tables(orc_sim* s)
@@ -151,6 +173,21 @@ static void build_tables(orc_sim* s)
     s->zsum = zsum;
     for (int m = 0; m < p->nvx * p->nvy; ++m)
         s->fsrc[m] = srcsum > 0.0 ? s->fsrc[m] / srcsum : 0.0;
+
+    /* Eq 5: full Maxwellian in both velocity components at T_e, normalised
+       on the grid so that its discrete integral is one (then the collision
+       term moves no electrons between planes) */
+    double eqsum = 0.0;
+    for (int i = 0; i < p->nvx; ++i)
+        for (int j = 0; j < p->nvy; ++j) {
+            double vx = s->vx[i], vy = s->vy[j];
+            size_t m = (size_t)i * p->nvy + j;
+            s->feq[m] = p->t_e_ev > 0.0
+                ? exp(-ORC_ME * (vx * vx + vy * vy) / (2.0 * p->t_e_ev * ORC_E)) : 0.0;
+            eqsum += s->feq[m] * s->dvx * s->dvy;
+        }
+    for (int m = 0; m < p->nvx * p->nvy; ++m)
+        s->feq[m] = eqsum > 0.0 ? s->feq[m] / eqsum : 0.0;
 
     for (int k = 0; k < p->nx; ++k) {
         double lo = k * s->dx, hi = (k + 1) * s->dx;
@@ -338,6 +375,24 @@ static double add_source(orc_sim* s, double* f)
     return injected * srcnorm;
 }
 
+/* Eq 3: the BGK collision increment dt nu_ee (n_e feq - f) of every cell,
+   from the state at the start of the step (f^n, and n^n from the prologue);
+   it is added to f after the sweeps and the source. */
+static void collision_increment(orc_sim* s)
+{
+    const orc_params* p = &s->p;
+    for (int k = 0; k < p->nx; ++k) {
+        double nk = s->ne[k];
+        double nudt = orc_nu_ee(nk, p->t_e_ev, p->ln_lambda) * s->dt;
+        if (nudt > s->nu_dt_max) s->nu_dt_max = nudt;
+        for (int i = 0; i < p->nvx; ++i)
+            for (int j = 0; j < p->nvy; ++j) {
+                size_t c = idx(s, k, i, j);
+                s->coll[c] = nudt * (nk * s->feq[(size_t)i * p->nvy + j] - s->f[c]);
+            }
+    }
+}
+
 /* ---- public API --------------------------------------------------------- */
 
 orc_sim* orc_create(const orc_params* p)
@@ -371,15 +426,18 @@ orc_sim* orc_create(const orc_params* p)
     s->delta = (double*)calloc(vcells, sizeof(double));
     s->ghat = (double*)calloc(vcells, sizeof(double));
     s->fsrc = (double*)calloc(vcells, sizeof(double));
+    s->feq = (double*)calloc(vcells, sizeof(double));
+    s->coll = (p->physics_mask & ORC_BGK) ? (double*)calloc(cells, sizeof(double)) : NULL;
     s->ghost = (double*)calloc(vcells, sizeof(double));
     s->wband = (double*)calloc(p->nx, sizeof(double));
     s->ne = (double*)calloc(p->nx, sizeof(double));
     s->ex = (double*)calloc(p->nx, sizeof(double));
     s->f = (double*)calloc(cells, sizeof(double));
     s->g = (double*)calloc(cells, sizeof(double));
-    if (!s->vx || !s->vy || !s->delta || !s->ghat || !s->fsrc || !s->ghost || !s->wband ||
-        !s->ne || !s->ex || !s->f || !s->g) {
-        free(s->vx); free(s->vy); free(s->delta); free(s->ghat); free(s->fsrc); free(s->ghost);
+    if (!s->vx || !s->vy || !s->delta || !s->ghat || !s->fsrc || !s->feq || !s->ghost || !s->wband ||
+        !s->ne || !s->ex || !s->f || !s->g || ((p->physics_mask & ORC_BGK) && !s->coll)) {
+        free(s->vx); free(s->vy); free(s->delta); free(s->ghat); free(s->fsrc); free(s->feq);
+        free(s->coll); free(s->ghost);
         free(s->wband); free(s->ne); free(s->ex); free(s->f); free(s->g); free(s);
         return NULL;
     }
@@ -390,7 +448,8 @@ orc_sim* orc_create(const orc_params* p)
 void orc_destroy(orc_sim* s)
 {
     if (!s) return;
-    free(s->vx); free(s->vy); free(s->delta); free(s->ghat); free(s->fsrc); free(s->ghost);
+    free(s->vx); free(s->vy); free(s->delta); free(s->ghat); free(s->fsrc); free(s->feq);
+    free(s->coll); free(s->ghost);
     free(s->wband); free(s->ne); free(s->ex); free(s->f); free(s->g); free(s);
 }
 
@@ -455,6 +514,8 @@ void orc_step(orc_sim* s, int64_t n, orc_record* trace)
             if ((p->physics_mask & ORC_VX) && d > s->cfl_max_vx) s->cfl_max_vx = d;
         }
 
+        if (p->physics_mask & ORC_BGK) collision_increment(s);
+
         double* a = s->f;
         double* b = s->g;
         double lost = 0.0, injected = 0.0;
@@ -462,6 +523,10 @@ void orc_step(orc_sim* s, int64_t n, orc_record* trace)
         if (p->physics_mask & ORC_VX) { lost += sweep_vx(s, a, b); double* t = a; a = b; b = t; }
         if (p->physics_mask & ORC_VY) { lost += sweep_vy(s, a, b); double* t = a; a = b; b = t; }
         if (p->physics_mask & ORC_SRC) injected = add_source(s, a);
+        if (p->physics_mask & ORC_BGK) {
+            size_t cells = (size_t)p->nx * p->nvx * p->nvy;
+            for (size_t c = 0; c < cells; ++c) a[c] += s->coll[c];
+        }
         s->f = a;
         s->g = b;
 
@@ -517,3 +582,11 @@ void orc_get_ghost(orc_sim* s, double* ghost)
 }
 
 double orc_cfl_max_vx(const orc_sim* s) { return s->cfl_max_vx; }
+
+double orc_nu_dt_max(const orc_sim* s) { return s->nu_dt_max; }
+
+/* The collisional equilibrium of Eq 5 on the grid (nvx*nvy). */
+void orc_get_feq(const orc_sim* s, double* out)
+{
+    memcpy(out, s->feq, (size_t)s->p.nvx * s->p.nvy * sizeof(double));
+}

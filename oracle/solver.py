@@ -16,6 +16,7 @@ EPS0 = 8.8541878128e-12
 
 X, VX, VY, SRC, SEE, SELF = 1, 2, 4, 8, 16, 32
 ALL = X | VX | VY | SRC | SEE | SELF
+BGK = 64   # electron-electron collisions (Eq 3-5); not part of ALL
 
 
 class _Params(C.Structure):
@@ -27,7 +28,7 @@ class _Params(C.Structure):
         ("t_se_ev", C.c_double), ("j_src", C.c_double), ("x_src_lo", C.c_double),
         ("x_src_hi", C.c_double), ("t_src_ev", C.c_double),
         ("emission_norm", C.c_int), ("physics_mask", C.c_uint),
-        ("ex_external", C.c_double),
+        ("ex_external", C.c_double), ("t_e_ev", C.c_double), ("ln_lambda", C.c_double),
     ]
 
 
@@ -70,6 +71,11 @@ def lib():
         L.orc_cfl_max_vx.argtypes = [C.c_void_p]
         L.orc_sey.restype = C.c_double
         L.orc_sey.argtypes = [C.c_double] * 5
+        L.orc_nu_ee.restype = C.c_double
+        L.orc_nu_ee.argtypes = [C.c_double] * 3
+        L.orc_nu_dt_max.restype = C.c_double
+        L.orc_nu_dt_max.argtypes = [C.c_void_p]
+        L.orc_get_feq.argtypes = [C.c_void_p, P(C.c_double)]
         _lib = L
     return _lib
 
@@ -81,6 +87,12 @@ def _ptr(a):
 def sey(delta_max, a_max_ev, ks, a_in_ev, alpha):
     """Eq 8-9 evaluated by the C oracle at one (energy, angle)."""
     return lib().orc_sey(delta_max, a_max_ev, ks, a_in_ev, alpha)
+
+
+def nu_ee(n_e, t_e_ev, ln_lambda):
+    """Eq 4 evaluated by the C oracle: collision frequency (1/s) at density
+    n_e (1/m^3) and temperature t_e_ev (eV)."""
+    return lib().orc_nu_ee(float(n_e), float(t_e_ev), float(ln_lambda))
 
 
 def set_threads(n):
@@ -175,3 +187,13 @@ class Oracle:
 
     def cfl_max_vx(self):
         return lib().orc_cfl_max_vx(self._h)
+
+    def nu_dt_max(self):
+        """Largest nu_ee dt of the collision steps so far."""
+        return lib().orc_nu_dt_max(self._h)
+
+    def feq(self):
+        """The collisional equilibrium of Eq 5 on the grid, normalised."""
+        out = np.empty((self.nvx, self.nvy))
+        lib().orc_get_feq(self._h, _ptr(out))
+        return out

@@ -17,6 +17,8 @@ Parameter keys (SI units unless the name says eV):
   emission_norm            0 discrete, 1 continuum prefactor of Eq 15
   physics_mask             bit set of the step's parts (values below)
   ex_external              uniform E_x added to the self field
+  t_e_ev, ln_lambda        temperature and Coulomb logarithm of the electron-
+                           electron collision term (Eq 3-5), used with BGK
 """
 import math
 
@@ -25,6 +27,7 @@ import numpy as np
 # Physics-mask bits (part of the parameter interface of both sides).
 X, VX, VY, SRC, SEE, SELF = 1, 2, 4, 8, 16, 32
 ALL = X | VX | VY | SRC | SEE | SELF
+BGK = 64   # electron-electron collisions; opt-in, not part of ALL
 
 _E = 1.602176634e-19
 _ME = 9.1093837015e-31
@@ -39,7 +42,7 @@ VMAX_1KEV = speed_of(1000.0)
 
 _BASE = dict(
     dt=0.0, cfl=0.9, ks=1.0, t_se_ev=2.0, j_src=1.0e5, x_src_lo=10e-6, x_src_hi=15e-6,
-    t_src_ev=2.0, emission_norm=0, physics_mask=ALL, ex_external=0.0,
+    t_src_ev=2.0, emission_norm=0, physics_mask=ALL, ex_external=0.0, t_e_ev=2.0, ln_lambda=10.0,
     vmax_x=VMAX_1KEV, vmax_y=VMAX_1KEV,
 )
 
