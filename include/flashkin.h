@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define FK_ABI_VERSION 2u   /* 2: fk_batch_info_t gained single_threads */
+#define FK_ABI_VERSION 3u   /* 2: fk_batch_info_t gained single_threads; 3: fk_params gained t_e_ev, ln_lambda */
 
 /* element type of f */
 enum { FK_F32 = 0, FK_F64 = 1 };
@@ -56,7 +56,14 @@ enum {
     FK_PHYS_SRC = 8,         /* band source (Eq 7) */
     FK_PHYS_SEE = 16,        /* secondary emission (Eq 8-16) */
     FK_PHYS_SELF_FIELD = 32, /* E_x from sigma and the electron space charge */
-    FK_PHYS_ALL = 63
+    FK_PHYS_ALL = 63,
+    /* Electron-electron collisions, the BGK term of Eq 3-5: each cell relaxes
+     * towards n_e(x) times the Maxwellian of Eq 5 at t_e_ev, at the frequency
+     * nu_ee(n_e) of Eq 4 with ln_lambda.  Opt-in (not part of FK_PHYS_ALL).
+     * Taken explicitly on f^n and n^n and added to the swept f; the
+     * Maxwellian is normalised on the grid, so the term moves no electrons
+     * between x planes.  Single contexts only (fk_batch_create rejects it). */
+    FK_PHYS_BGK = 64
 };
 
 /* error codes */
@@ -65,7 +72,7 @@ enum {
     FK_E_INVALID = -1,   /* bad argument or parameter */
     FK_E_OOM = -2,       /* device or host allocation failed */
     FK_E_HIP = -3,       /* a HIP runtime call failed */
-    FK_E_CFL = -4,       /* a Courant number exceeded one (sticky until fk_write_state) */
+    FK_E_CFL = -4,       /* a Courant number, or nu_ee dt with FK_PHYS_BGK, exceeded one (sticky until fk_write_state) */
     FK_E_NONFINITE = -5, /* a moment or flux became NaN/Inf (sticky until fk_write_state) */
     FK_E_STATE = -6      /* call not valid in the object's current state */
 };
@@ -97,6 +104,8 @@ typedef struct {
     int32_t trace_cap;       /* records held on the device between drains (>= 1) */
     int32_t tile_rows;       /* v_x rows per tile: 4, 8, 12 or 16 (12 and 16: FK_F32, nvy <= 512), 0 = library choice */
     int32_t tile_planes;     /* x planes per tile; 0: chosen at creation from the sweep kernel's occupancy: the longest run (16..128) that keeps 8 waves resident per compute unit, or all a unit holds, with the workgroups spread evenly (fk_validate reports a host-side estimate, fk_query the choice); batch instances get 16 */
+    double t_e_ev;           /* FK_PHYS_BGK: temperature of the collisional equilibrium (Eq 4-5), eV, > 0 */
+    double ln_lambda;        /* FK_PHYS_BGK: Coulomb logarithm of Eq 4 (the paper: 10), > 0 */
 } fk_params;
 
 /* Observables of the state (f^n, sigma^n) after n steps.  The fluxes are
@@ -245,7 +254,7 @@ int fk_autotune(fk_ctx* ctx, int trial_steps, fk_info* chosen);
  * x chunk, v_x tiles) work items largest first from an atomic counter; one
  * field launch then reduces and solves every instance (a workgroup each);
  * steps are replayed from HIP graphs.  Every instance is FK_F32 with
- * nvy <= 256 and starts at f = 0, sigma = 0.
+ * nvy <= 256, without FK_PHYS_BGK, and starts at f = 0, sigma = 0.
  *   mode 0: split launches: up to four sweep launches per step, by tile
  *           body and workgroup width;
  *   mode 1: autotune: time short trial runs of tilings, grid sizes, item

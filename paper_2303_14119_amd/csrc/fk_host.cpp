@@ -19,10 +19,15 @@ int set_error(std::string* slot, int code, const std::string& msg)
     return code;
 }
 
-static size_t sweep_lds(int ti, int block, int kc, int elem)
+// LDS of a sweep workgroup: the v_y exchange rows, the plane sums, the
+// reduction slots and each wave's table of per-plane coefficients (2 per
+// plane; with the collision term 4 per plane and the tile's rows of the
+// v_x factor of the equilibrium)
+size_t sweep_lds(int ti, int block, int kc, int elem, bool bgk)
 {
     const int waves = (block + 63) / 64;
-    return (size_t)2 * ti * (block + 2) * elem + (size_t)kc * waves * 8 + (size_t)waves * 4 * 8 + (size_t)waves * 2 * kc * elem;
+    const size_t tab = bgk ? (size_t)4 * kc + ti : (size_t)2 * kc;
+    return (size_t)2 * ti * (block + 2) * elem + (size_t)kc * waves * 8 + (size_t)waves * 4 * 8 + (size_t)waves * tab * elem;
 }
 
 int derive_layout(const fk_params* p, Layout* L, std::string* why)
@@ -43,7 +48,10 @@ int derive_layout(const fk_params* p, Layout* L, std::string* why)
     if (!(p->j_src >= 0) || !std::isfinite(p->j_src)) return bad("j_src must be >= 0");
     if (!(p->x_src_hi >= p->x_src_lo)) return bad("x_src_hi must be >= x_src_lo");
     if (p->emission_norm != FK_EMIT_DISCRETE && p->emission_norm != FK_EMIT_ANALYTIC) return bad("bad emission_norm");
-    if (p->physics_mask & ~(uint32_t)FK_PHYS_ALL) return bad("unknown physics_mask bits");
+    if (p->physics_mask & ~(uint32_t)(FK_PHYS_ALL | FK_PHYS_BGK)) return bad("unknown physics_mask bits");
+    const bool bgk = (p->physics_mask & FK_PHYS_BGK) != 0;
+    if (bgk && !(p->t_e_ev > 0 && std::isfinite(p->t_e_ev))) return bad("t_e_ev must be > 0 and finite with FK_PHYS_BGK");
+    if (bgk && !(p->ln_lambda > 0 && std::isfinite(p->ln_lambda))) return bad("ln_lambda must be > 0 and finite with FK_PHYS_BGK");
     if (p->trace_stride < 1 || p->trace_cap < 1) return bad("trace_stride and trace_cap must be >= 1");
     if (p->tile_rows != 0 && p->tile_rows != 4 && p->tile_rows != 8 && p->tile_rows != 12 && p->tile_rows != 16)
         return bad("tile_rows must be 0, 4, 8, 12 or 16");
@@ -59,6 +67,7 @@ int derive_layout(const fk_params* p, Layout* L, std::string* why)
     Layout l{};
     l.cells = cells;
     l.elem = p->dtype == FK_F32 ? 4 : 8;
+    l.bgk = bgk ? 1 : 0;
     l.dx = p->length_m / p->nx;
     l.dvx = 2.0 * p->vmax_x / p->nvx;
     l.dvy = 2.0 * p->vmax_y / p->nvy;
@@ -94,10 +103,10 @@ int derive_layout(const fk_params* p, Layout* L, std::string* why)
         // 24); otherwise the generic body on split tiles costs more.
         // FP64: 4 rows.
         ti = l.elem == 4 ? 8 : 4;
-        if (l.elem == 4 && l.block >= 320 && l.block <= 512 && sweep_lds(16, l.block, 16, l.elem) <= kLdsBudget)
+        if (l.elem == 4 && l.block >= 320 && l.block <= 512 && sweep_lds(16, l.block, 16, l.elem, bgk) <= kLdsBudget)
             ti = 16;
-        if (ti == 16 && p->nvx % 24 == 0 && sweep_lds(12, l.block, 16, l.elem) <= kLdsBudget) ti = 12;
-        while (ti > 4 && sweep_lds(ti, l.block, 16, l.elem) > kLdsBudget) ti /= 2;
+        if (ti == 16 && p->nvx % 24 == 0 && sweep_lds(12, l.block, 16, l.elem, bgk) <= kLdsBudget) ti = 12;
+        while (ti > 4 && sweep_lds(ti, l.block, 16, l.elem, bgk) > kLdsBudget) ti /= 2;
     }
     if (ti == 16 && (l.elem != 4 || l.block > 512)) return bad("tile_rows 16 needs FK_F32 and nvy <= 512");
     if (ti == 12 && (l.elem != 4 || l.block > 512)) return bad("tile_rows 12 needs FK_F32 and nvy <= 512");
@@ -113,7 +122,7 @@ int derive_layout(const fk_params* p, Layout* L, std::string* why)
         kc = (p->nx + nkc - 1) / nkc;
         if (kc < 16) kc = 16;
         if (kc > 128) kc = 128;
-        while (kc > 16 && sweep_lds(ti, l.block, kc, l.elem) > kLdsBudget) kc -= 16;
+        while (kc > 16 && sweep_lds(ti, l.block, kc, l.elem, bgk) > kLdsBudget) kc -= 16;
     }
     if (kc > p->nx) kc = p->nx;
     l.kc = kc;
@@ -122,7 +131,7 @@ int derive_layout(const fk_params* p, Layout* L, std::string* why)
     l.n_fast = 0;
     for (int it = 0; it < l.n_it; ++it) l.n_fast += tile_is_fast(it, ti, p->nvx) ? 1 : 0;
     l.n_generic = l.n_it - l.n_fast;
-    l.lds_sweep = sweep_lds(ti, l.block, kc, l.elem);
+    l.lds_sweep = sweep_lds(ti, l.block, kc, l.elem, bgk);
     l.lds_moments = (size_t)kc * (l.block / 64) * 8 + (size_t)(l.block / 64) * 4 * 8;
     if (l.lds_sweep > kLdsBudget) return bad("tile needs more LDS than a workgroup has; lower tile_rows or tile_planes");
 
@@ -131,7 +140,8 @@ int derive_layout(const fk_params* p, Layout* L, std::string* why)
     l.n_it_cap = (p->nvx + 3) / 4;
     l.nwg_cap = l.n_it_cap * ((p->nx + 3) / 4);
     const uint64_t v2 = (uint64_t)p->nvx * p->nvy;
-    l.bytes_device = 2ull * cells * l.elem + v2 * (8 * 3 + l.elem) + (uint64_t)p->nx * 8 * 7 +
+    l.bytes_device = 2ull * cells * l.elem + v2 * (8 * 3 + l.elem) + (uint64_t)p->nx * 8 * 9 +
+                     (uint64_t)(p->nvx + p->nvy) * l.elem +
                      (uint64_t)p->nx * l.n_it_cap * 8 + (uint64_t)l.n_it_cap * 28 + (uint64_t)l.nwg_cap * 8 +
                      sizeof(DevState) + (uint64_t)p->trace_cap * sizeof(fk_state) + 4096;
     *L = l;

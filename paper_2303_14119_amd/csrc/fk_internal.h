@@ -44,6 +44,7 @@ struct Layout {
     double dy;                   // signed v_y Courant number a_y dt / dv_y
     int64_t cells;
     int elem;                    // bytes per f element
+    int bgk;                     // 1: the collision term (FK_PHYS_BGK) is on
     int block;                   // threads of the sweep workgroup (one per v_y column)
     int ti;                      // v_x rows per tile
     int kc;                      // x planes per tile
@@ -55,6 +56,7 @@ struct Layout {
 };
 
 int derive_layout(const fk_params* p, Layout* L, std::string* why);
+size_t sweep_lds(int ti, int block, int kc, int elem, bool bgk);
 
 // Number of rows among r = 0..ti+1 of v_x tile `it` (rows i = it*ti - 1 + r)
 // with v_x <= 0, i.e. 2 i + 1 <= nvx: the split point of the fast sweep body.
@@ -103,6 +105,10 @@ struct Buffers {
     double* ne;       // [nx]
     double* ex;       // [nx]
     double* dxk;      // [nx], v_x Courant number of each plane
+    double* nudt;     // [nx], nu_ee(n_k) dt of each plane (collision term)
+    double* nudt_n;   // [nx], nu_ee(n_k) dt n_k
+    void* gx;         // [nvx], v_x factor of the normalised equilibrium, element type of f
+    void* gy;         // [nvy], v_y factor
     double* consts;   // [4]: zsum, srcnorm, injected per step, emission prefactor
     int* tiles;       // [n_it]: fast v_x tiles, then generic ones
     DevState* st;

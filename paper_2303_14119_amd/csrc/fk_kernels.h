@@ -122,6 +122,10 @@ struct SweepArgs {
     const double* __restrict__ dxk;     // [nx] v_x Courant number per plane (0 if v_x advection off)
     const double* __restrict__ srck;    // [nx] source coefficient per plane (0 outside the band)
     const T* __restrict__ fsrc;         // [nvx][nvy] normalised source VDF
+    const double* __restrict__ nudt;    // [nx] nu_ee dt per plane (collision term, Eq 3-4)
+    const double* __restrict__ nudt_n;  // [nx] nu_ee dt n_e per plane
+    const T* __restrict__ gx;           // [nvx] v_x factor of the normalised equilibrium (Eq 5)
+    const T* __restrict__ gy;           // [nvy] v_y factor
     const double* __restrict__ ghat;    // [nvx][nvy] emission shape
     const double* __restrict__ delta;   // [nvx][nvy] SEY
     const DevState* __restrict__ st;    // gscale of this step
@@ -185,7 +189,7 @@ template <typename T, int CP = kCpDefault> __device__ __forceinline__ void bstor
 // f is read once and written once per cell, plus the two halo rows (mostly
 // L2 hits: the neighbouring tiles run on the same XCD) and one halo plane per
 // chunk.
-template <typename T, int TI, bool EDGE>
+template <typename T, int TI, bool EDGE, bool BGK = false>
 __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, int it, int kci, double* smem, int j, int B)
 {
     const int i0 = it * TI;
@@ -275,10 +279,21 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, int it, int kc
     // memory operation but its plane loads and stores, so the compiler's
     // waits for the prefetched plane never cover a later load.  A wave reads
     // only what its own lanes wrote, so no workgroup barrier is needed.
-    T* tab = reinterpret_cast<T*>(red + nw * 4) + wave * 2 * a.kc;   // [nw][2][kc]
+    // With the collision term the table also holds nu_ee dt and nu_ee dt n_e
+    // per plane and the tile's rows of the equilibrium's v_x factor.
+    T* tab = reinterpret_cast<T*>(red + nw * 4) + wave * (BGK ? 4 * a.kc + TI : 2 * a.kc);
     for (int m = lane; m < k1 - k0; m += 64) {
         tab[m] = T(a.dxk[k0 + m]);
         tab[a.kc + m] = T(a.srck[k0 + m]);
+        if (BGK) {
+            tab[2 * a.kc + m] = T(a.nudt[k0 + m]);
+            tab[3 * a.kc + m] = T(a.nudt_n[k0 + m]);
+        }
+    }
+    T gyj = T(0);
+    if (BGK) {
+        for (int m = lane; m < TI; m += 64) tab[4 * a.kc + m] = i0 + m < a.nvx ? a.gx[i0 + m] : T(0);
+        gyj = jok ? a.gy[j] : T(0);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -337,6 +352,17 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, int it, int kc
 #pragma unroll
             for (int r = 0; r < TI; ++r)
                 if (rv[r + 1] && jok) f3[r] += ts * a.fsrc[(size_t)(i0 + r) * a.nvy + j];
+        }
+
+        // electron-electron collisions (Eq 3): dt nu_ee (n_e gx gy - f^n).
+        // Rows outside the grid and idle lanes have gx, gy and f^n all 0.
+        if (BGK) {
+            const T bk = tab[2 * a.kc + k - k0];
+            if (bk != T(0)) {
+                const T agy = tab[3 * a.kc + k - k0] * gyj;
+#pragma unroll
+                for (int r = 0; r < TI; ++r) f3[r] += agy * tab[4 * a.kc + r] - bk * fc[r + 1];
+            }
         }
 
         {
@@ -511,12 +537,15 @@ struct FieldArgs {
     double* __restrict__ ne;
     double* __restrict__ ex;
     double* __restrict__ dxk;
+    double* __restrict__ nudt;      // [nx] out: nu_ee dt per plane (collision term)
+    double* __restrict__ nudt_n;    // [nx] out: nu_ee dt n_e per plane
     DevState* __restrict__ st;
     fk_state* __restrict__ ring;
     int nx, n_it, nwg, advance;
     uint32_t mask;
     int emission_norm, trace_stride, trace_cap;
     double dx, dv2, dt, dvx, ex_ext;
+    double nudt_per_n;              // dt nu_ee / n_e of Eq 4 (0: no collision term)
 };
 
 // Reduction of the moment partials of the new f over the v_x tiles (fixed
@@ -614,17 +643,17 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
     double excl = __shfl_up(incl, 1, 64);
     if (lane == 0) excl = 0.0;
     double* wtot = sh;              // [nw]
-    double* red = sh + 64;          // [nw][5]
+    double* red = sh + 64;          // [nw][6]
     if (lane == 63) wtot[wave] = incl;
     pe = wave_sum(pe);
     see = wave_sum(see);
     top = wave_sum(top);
     lv = wave_sum(lv);
     if (lane == 0) {
-        red[wave * 5 + 0] = pe;
-        red[wave * 5 + 1] = see;
-        red[wave * 5 + 2] = top;
-        red[wave * 5 + 3] = lv;
+        red[wave * 6 + 0] = pe;
+        red[wave * 6 + 1] = see;
+        red[wave * 6 + 2] = top;
+        red[wave * 6 + 3] = lv;
     }
     __syncthreads();
     double wave_below = 0.0, total = 0.0;
@@ -646,7 +675,7 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
     const double sigma_now = sig + sig_lo;
 
     // E_x at the cell centres: sigma / 2 eps0 minus the electron charge below
-    double run = below0, cmax = 0.0;
+    double run = below0, cmax = 0.0, bmax = 0.0;
     const double e_wall = sigma_now / (2.0 * kEps0), e_per_n = kE / kEps0 * a.dx;
     const double d_per_e = (a.mask & FK_PHYS_VX) ? -kE / kMe * a.dt / a.dvx : 0.0;   // Courant number per V/m
     auto field_at = [&](int k, double nk) {
@@ -656,6 +685,13 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
         const double d = d_per_e * e;
         a.dxk[k] = d;
         cmax = fmax(cmax, fabs(d));
+        if (a.nudt_per_n != 0.0) {
+            // collision term of the next step (Eq 3-4): nu_ee is linear in n_e
+            const double b = a.nudt_per_n * nk;
+            a.nudt[k] = b;
+            a.nudt_n[k] = b * nk;
+            bmax = fmax(bmax, b);
+        }
         run += nk;
     };
     if (in_regs) {
@@ -669,16 +705,21 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
         for (int k = kb; k < ke; ++k) field_at(k, a.ne[k]);
     }
     cmax = wave_max_nonneg(cmax);
-    if (lane == 0) red[wave * 5 + 4] = cmax;
+    bmax = wave_max_nonneg(bmax);
+    if (lane == 0) {
+        red[wave * 6 + 4] = cmax;
+        red[wave * 6 + 5] = bmax;
+    }
     __syncthreads();
     if (t == 0) {
-        pe = see = top = lv = cmax = 0.0;
+        pe = see = top = lv = cmax = bmax = 0.0;
         for (int w = 0; w < nw; ++w) {
-            pe += red[w * 5 + 0];
-            see += red[w * 5 + 1];
-            top += red[w * 5 + 2];
-            lv += red[w * 5 + 3];
-            cmax = fmax(cmax, red[w * 5 + 4]);
+            pe += red[w * 6 + 0];
+            see += red[w * 6 + 1];
+            top += red[w * 6 + 2];
+            lv += red[w * 6 + 3];
+            cmax = fmax(cmax, red[w * 6 + 4]);
+            bmax = fmax(bmax, red[w * 6 + 5]);
         }
     }
 
@@ -714,7 +755,7 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
         ns.resid = resid;
         ns.gscale = gscale;
         ns.courant_vx_max = fmax(old.courant_vx_max, cmax);
-        if (cmax > 1.0) ns.flags |= kFlagCfl;
+        if (cmax > 1.0 || bmax > 1.0) ns.flags |= kFlagCfl;
         if (!isfinite(n_total) || !isfinite(g_pe) || !isfinite(g_see) || !isfinite(g_top) ||
             !isfinite(sigma_now))
             ns.flags |= kFlagNonfinite;

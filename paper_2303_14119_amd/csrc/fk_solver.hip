@@ -25,13 +25,35 @@ struct TableArgs {
     double* srck;
     double* consts;
     void* fsrc;
+    void* gx;
+    void* gy;
     int is_f32;
     int nx, nvx, nvy;
     double vmax_x, vmax_y, dvx, dvy, dx, dt;
-    double delta_max, a_max_ev, ks, t_se_ev, t_src_ev;
+    double delta_max, a_max_ev, ks, t_se_ev, t_src_ev, t_e_ev;
     double j_src, x_lo, x_hi;
     uint32_t mask;
 };
+
+// One velocity axis of the collisional equilibrium (Eq 5 is a product of a
+// v_x and a v_y Maxwellian at T_e): exp(-m v^2 / 2 T_e) normalised so that
+// its sum times dv is one, written in f's element type.  The product of
+// the two factors then has unit discrete integral over the grid.
+__device__ void equilibrium_axis(int n, double dv, double t_ev, bool on, int is_f32, void* out, double* sh)
+{
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double v = cell_v(i, n, dv);
+        s += on ? exp(-kMe * v * v / (2.0 * t_ev * kE)) * dv : 0.0;
+    }
+    s = block_sum(s, sh);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double v = cell_v(i, n, dv);
+        const double g = (on && s > 0.0) ? exp(-kMe * v * v / (2.0 * t_ev * kE)) / s : 0.0;
+        if (is_f32) static_cast<float*>(out)[i] = (float)g;
+        else static_cast<double*>(out)[i] = g;
+    }
+}
 
 // SEY of Eq 8-9 at incident energy a_ev (Eq 10) and angle alpha (Eq 11).
 __device__ double sey_yield(double delta_max, double a_max_ev, double ks, double a_ev, double alpha)
@@ -110,6 +132,9 @@ __global__ void __launch_bounds__(kFieldThreads) k_tables_norm(TableArgs a)
         const double mt = kMe / (a.t_se_ev * kE);
         a.consts[3] = pow(mt, 1.5) / sqrt(2.0 * kPi);   // Eq 15 prefactor per unit Gamma_see
     }
+    const bool bgk = (a.mask & FK_PHYS_BGK) && a.t_e_ev > 0.0;
+    equilibrium_axis(a.nvx, a.dvx, a.t_e_ev, bgk, a.is_f32, a.gx, sh);
+    equilibrium_axis(a.nvy, a.dvy, a.t_e_ev, bgk, a.is_f32, a.gy, sh);
 }
 
 // ---------------------------------------------------------------- kernels
@@ -259,6 +284,10 @@ SweepArgs<T> sweep_args(const fk_ctx* c, int from)
     a.dxk = c->b.dxk;
     a.srck = c->b.srck;
     a.fsrc = static_cast<const T*>(c->b.fsrc);
+    a.nudt = c->b.nudt;
+    a.nudt_n = c->b.nudt_n;
+    a.gx = static_cast<const T*>(c->b.gx);
+    a.gy = static_cast<const T*>(c->b.gy);
     a.ghat = c->b.ghat;
     a.delta = c->b.delta;
     a.st = c->b.st;
@@ -287,22 +316,29 @@ SweepArgs<T> sweep_args(const fk_ctx* c, int from)
     return a;
 }
 
-template <typename T, int TI, int MAXB>
-void launch_sweep_t(const fk_ctx* c, int from, hipStream_t s)
+template <typename T, int TI, int MAXB, bool BGK>
+void launch_sweep_b(const fk_ctx* c, int from, hipStream_t s)
 {
     SweepArgs<T> a = sweep_args<T>(c, from);
     if (c->L.n_fast > 0) {
         a.tile_list = c->b.tiles;
         a.n_list = c->L.n_fast;
-        hipLaunchKernelGGL((k_sweep<T, TI, MAXB>), dim3(c->L.n_fast * c->L.n_kc), dim3(c->L.block),
+        hipLaunchKernelGGL((k_sweep<T, TI, MAXB, BGK>), dim3(c->L.n_fast * c->L.n_kc), dim3(c->L.block),
                            c->L.lds_sweep, s, a);
     }
     if (c->L.n_generic > 0) {
         a.tile_list = c->b.tiles + c->L.n_fast;
         a.n_list = c->L.n_generic;
-        hipLaunchKernelGGL((k_sweep_generic<T, TI, MAXB>), dim3(c->L.n_generic * c->L.n_kc),
+        hipLaunchKernelGGL((k_sweep_generic<T, TI, MAXB, BGK>), dim3(c->L.n_generic * c->L.n_kc),
                            dim3(c->L.block), c->L.lds_sweep, s, a);
     }
+}
+
+template <typename T, int TI, int MAXB>
+void launch_sweep_t(const fk_ctx* c, int from, hipStream_t s)
+{
+    if (c->L.bgk) launch_sweep_b<T, TI, MAXB, true>(c, from, s);
+    else launch_sweep_b<T, TI, MAXB, false>(c, from, s);
 }
 
 void launch_sweep(const fk_ctx* c, int from, hipStream_t s)
@@ -355,6 +391,8 @@ FieldArgs field_args(const fk_ctx* c, int advance)
     a.ne = c->b.ne;
     a.ex = c->b.ex;
     a.dxk = c->b.dxk;
+    a.nudt = c->b.nudt;
+    a.nudt_n = c->b.nudt_n;
     a.st = c->b.st;
     a.ring = c->b.ring;
     a.nx = c->p.nx;
@@ -368,6 +406,12 @@ FieldArgs field_args(const fk_ctx* c, int advance)
     a.dt = c->L.dt;
     a.dvx = c->L.dvx;
     a.ex_ext = c->p.ex_external;
+    if (c->L.bgk) {
+        // Eq 4: nu_ee = n_e e^4 ln(Lambda) / (12 pi^1.5 eps0^2 sqrt(m_e) T_e^1.5), T_e in joules
+        const double te = c->p.t_e_ev * kE;
+        a.nudt_per_n = c->L.dt * kE * kE * kE * kE * c->p.ln_lambda /
+                       (12.0 * pow(kPi, 1.5) * kEps0 * kEps0 * sqrt(kMe) * te * sqrt(te));
+    }
     return a;
 }
 
@@ -417,6 +461,8 @@ int alloc_buffers(fk_ctx* c, void* fa, void* fb)
                  o_pn = take((size_t)p.nx * L.n_it_cap * 8), o_pw = take((size_t)L.n_it_cap * 16),
                  o_pt = take((size_t)L.n_it_cap * 8), o_plv = take((size_t)L.nwg_cap * 8),
                  o_ne = take(p.nx * 8), o_ex = take(p.nx * 8), o_dxk = take(p.nx * 8),
+                 o_nudt = take(p.nx * 8), o_nudtn = take(p.nx * 8), o_gx = take((size_t)p.nvx * L.elem),
+                 o_gy = take((size_t)p.nvy * L.elem),
                  o_consts = take(64), o_tiles = take((size_t)L.n_it_cap * sizeof(int)),
                  o_psum = take((size_t)p.nx * 8), o_st = take(sizeof(DevState)),
                  o_ring = take((size_t)p.trace_cap * sizeof(fk_state));
@@ -438,6 +484,10 @@ int alloc_buffers(fk_ctx* c, void* fa, void* fb)
     c->b.ne = (double*)(base + o_ne);
     c->b.ex = (double*)(base + o_ex);
     c->b.dxk = (double*)(base + o_dxk);
+    c->b.nudt = (double*)(base + o_nudt);
+    c->b.nudt_n = (double*)(base + o_nudtn);
+    c->b.gx = base + o_gx;
+    c->b.gy = base + o_gy;
     c->b.consts = (double*)(base + o_consts);
     c->b.tiles = (int*)(base + o_tiles);
     c->b.plane_sum = (double*)(base + o_psum);
@@ -480,6 +530,8 @@ int build_tables(fk_ctx* c)
     a.srck = c->b.srck;
     a.consts = c->b.consts;
     a.fsrc = c->b.fsrc;
+    a.gx = c->b.gx;
+    a.gy = c->b.gy;
     a.is_f32 = c->L.elem == 4;
     a.nx = p.nx;
     a.nvx = p.nvx;
@@ -495,6 +547,7 @@ int build_tables(fk_ctx* c)
     a.ks = p.ks;
     a.t_se_ev = p.t_se_ev;
     a.t_src_ev = p.t_src_ev;
+    a.t_e_ev = p.t_e_ev;
     a.j_src = p.j_src;
     a.x_lo = p.x_src_lo;
     a.x_hi = p.x_src_hi;
@@ -660,26 +713,32 @@ std::vector<std::pair<int, int>> tile_candidates(const fk_params& p)
 }
 
 // Workgroups of a layout's main sweep kernel that fit on one compute unit.
-int sweep_wgs_per_cu(const Layout& L)
+template <bool BGK>
+int sweep_wgs_per_cu_b(const Layout& L)
 {
     int occ = 0;
     hipError_t e;
     const bool small = L.block <= 512;
     if (L.elem == 4) {
         if (L.ti == 16)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sweep<float, 16, 512>, L.block, L.lds_sweep);
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sweep<float, 16, 512, BGK>, L.block, L.lds_sweep);
         else if (L.ti == 12)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sweep<float, 12, 512>, L.block, L.lds_sweep);
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sweep<float, 12, 512, BGK>, L.block, L.lds_sweep);
         else if (L.ti == 8)
-            e = small ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sweep<float, 8, 512>, L.block, L.lds_sweep)
-                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sweep<float, 8, 1024>, L.block, L.lds_sweep);
+            e = small ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sweep<float, 8, 512, BGK>, L.block, L.lds_sweep)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sweep<float, 8, 1024, BGK>, L.block, L.lds_sweep);
         else
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sweep<float, 4, 1024>, L.block, L.lds_sweep);
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sweep<float, 4, 1024, BGK>, L.block, L.lds_sweep);
     } else {
-        e = L.ti == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sweep<double, 8, 512>, L.block, L.lds_sweep)
-                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sweep<double, 4, 1024>, L.block, L.lds_sweep);
+        e = L.ti == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sweep<double, 8, 512, BGK>, L.block, L.lds_sweep)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sweep<double, 4, 1024, BGK>, L.block, L.lds_sweep);
     }
     return e == hipSuccess ? occ : 0;
+}
+
+int sweep_wgs_per_cu(const Layout& L)
+{
+    return L.bgk ? sweep_wgs_per_cu_b<true>(L) : sweep_wgs_per_cu_b<false>(L);
 }
 
 // x planes per tile when the caller leaves it open, among 16 .. 128 (steps
@@ -855,7 +914,7 @@ extern "C" int fk_sync(fk_ctx* c)
     int code = flags_to_code(s.flags);
     if (code) {
         c->sticky = code;
-        return set_error(&c->err, code, code == FK_E_CFL ? "v_x Courant number above one (E_x too strong for dt)"
+        return set_error(&c->err, code, code == FK_E_CFL ? "v_x Courant number or nu_ee dt above one (E_x or n_e too large for dt)"
                                                           : "non-finite moment, flux or surface charge");
     }
     return FK_OK;
@@ -1450,6 +1509,8 @@ extern "C" int fk_batch_create(const fk_params* params, int n, void* stream, int
         int rc = derive_layout(&params[m], &L, &why);
         if (rc) return set_error(nullptr, rc, "instance " + std::to_string(m) + ": " + why);
         if (params[m].dtype != FK_F32) return set_error(nullptr, FK_E_INVALID, "batched instances are FK_F32");
+        if (params[m].physics_mask & FK_PHYS_BGK)
+            return set_error(nullptr, FK_E_INVALID, "batched instances do not take the collision term (FK_PHYS_BGK)");
         if (L.block > kBatchThreads) return set_error(nullptr, FK_E_INVALID, "batched instances need nvy <= 256");
     }
     fk_batch* b = new (std::nothrow) fk_batch();

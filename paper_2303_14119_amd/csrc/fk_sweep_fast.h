@@ -23,7 +23,7 @@
 
 namespace fk {
 
-template <typename T, int TI, int S, bool RAGGED = false>
+template <typename T, int TI, int S, bool RAGGED = false, bool BGK = false>
 __device__ __forceinline__ void sweep_fast(const SweepArgs<T>& a, int it, int kci, double* smem, int j, int B)
 {
     const int i0 = it * TI;
@@ -114,10 +114,21 @@ __device__ __forceinline__ void sweep_fast(const SweepArgs<T>& a, int it, int kc
     // memory operation but its plane loads and stores, so the compiler's
     // waits for the prefetched plane never cover a later load.  A wave reads
     // only what its own lanes wrote, so no workgroup barrier is needed.
-    T* tab = reinterpret_cast<T*>(red + nw * 4) + wave * 2 * a.kc;   // [nw][2][kc]
+    // With the collision term the table also holds nu_ee dt and nu_ee dt n_e
+    // per plane and the tile's rows of the equilibrium's v_x factor.
+    T* tab = reinterpret_cast<T*>(red + nw * 4) + wave * (BGK ? 4 * a.kc + TI : 2 * a.kc);
     for (int m = lane; m < k1 - k0; m += 64) {
         tab[m] = T(a.dxk[k0 + m]);
         tab[a.kc + m] = T(a.srck[k0 + m]);
+        if (BGK) {
+            tab[2 * a.kc + m] = T(a.nudt[k0 + m]);
+            tab[3 * a.kc + m] = T(a.nudt_n[k0 + m]);
+        }
+    }
+    T gyj = T(0);
+    if (BGK) {
+        for (int m = lane; m < TI; m += 64) tab[4 * a.kc + m] = i0 + m < a.nvx ? a.gx[i0 + m] : T(0);
+        gyj = jok ? a.gy[j] : T(0);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -197,6 +208,18 @@ __device__ __forceinline__ void sweep_fast(const SweepArgs<T>& a, int it, int kc
 #pragma unroll
             for (int r = 0; r < TI; ++r)
                 f3[r] += ts * (RAGGED ? bload<T>(psrc, roff(r + 1), 0) : bload<T>(psrc, vb, r * rb));
+        }
+
+        // electron-electron collisions (Eq 3): dt nu_ee (n_e gx gy - f^n),
+        // with f^n of output row r in w0 (v_x <= 0) or w1 (v_x > 0).  Rows
+        // past the grid and idle lanes have gx, gy and f^n all 0.
+        if (BGK) {
+            const T bk = tab[2 * a.kc + k - k0];
+            if (bk != T(0)) {
+                const T agy = tab[3 * a.kc + k - k0] * gyj;
+#pragma unroll
+                for (int r = 0; r < TI; ++r) f3[r] += agy * tab[4 * a.kc + r] - bk * (r + 1 < S ? w0[r + 1] : w1[r + 1]);
+            }
         }
 
         {
@@ -280,64 +303,66 @@ __device__ __forceinline__ void sweep_fast(const SweepArgs<T>& a, int it, int kc
     }
 }
 
-template <typename T, int TI>
+template <typename T, int TI, bool BGK = false>
 __device__ __forceinline__ void sweep_fast_dispatch(const SweepArgs<T>& a, int it, int kci, double* smem, int j, int B)
 {
     switch (tile_split(it, TI, a.nvx)) {
-    case 0: sweep_fast<T, TI, 0>(a, it, kci, smem, j, B); break;
-    case 1: sweep_fast<T, TI, 1>(a, it, kci, smem, j, B); break;
-    case TI + 1: sweep_fast<T, TI, TI + 1>(a, it, kci, smem, j, B); break;
-    default: sweep_fast<T, TI, TI + 2>(a, it, kci, smem, j, B); break;
+    case 0: sweep_fast<T, TI, 0, false, BGK>(a, it, kci, smem, j, B); break;
+    case 1: sweep_fast<T, TI, 1, false, BGK>(a, it, kci, smem, j, B); break;
+    case TI + 1: sweep_fast<T, TI, TI + 1, false, BGK>(a, it, kci, smem, j, B); break;
+    default: sweep_fast<T, TI, TI + 2, false, BGK>(a, it, kci, smem, j, B); break;
     }
 }
 
 // Splits inside the tile (S = 2 .. TI) as a chain of uniform branches.
-template <typename T, int TI, int S>
+template <typename T, int TI, int S, bool BGK = false>
 __device__ __forceinline__ void sweep_mid_chain(const SweepArgs<T>& a, int it, int kci, double* smem, int j, int B,
                                                 int s)
 {
     if constexpr (S == TI) {
-        sweep_fast<T, TI, S>(a, it, kci, smem, j, B);
+        sweep_fast<T, TI, S, false, BGK>(a, it, kci, smem, j, B);
     } else {
-        if (s == S) sweep_fast<T, TI, S>(a, it, kci, smem, j, B);
-        else sweep_mid_chain<T, TI, S + 1>(a, it, kci, smem, j, B, s);
+        if (s == S) sweep_fast<T, TI, S, false, BGK>(a, it, kci, smem, j, B);
+        else sweep_mid_chain<T, TI, S + 1, BGK>(a, it, kci, smem, j, B, s);
     }
 }
 
 // Tiles outside the edge-split set: the fast body compiled for their split
 // (full tiles of 4 or 8 rows split inside the tile) or for a ragged last
 // tile whose rows all have v_x > 0; any other tile takes the generic body.
-template <typename T, int TI>
+template <typename T, int TI, bool BGK = false>
 __device__ __forceinline__ void sweep_rest(const SweepArgs<T>& a, int it, int kci, double* smem, int j, int B)
 {
     if constexpr (TI == 4 || TI == 8) {
         if (tile_is_special(it, TI, a.nvx)) {
-            if ((it + 1) * TI > a.nvx) sweep_fast<T, TI, 0, true>(a, it, kci, smem, j, B);
-            else sweep_mid_chain<T, TI, 2>(a, it, kci, smem, j, B, tile_split(it, TI, a.nvx));
+            if ((it + 1) * TI > a.nvx) sweep_fast<T, TI, 0, true, BGK>(a, it, kci, smem, j, B);
+            else sweep_mid_chain<T, TI, 2, BGK>(a, it, kci, smem, j, B, tile_split(it, TI, a.nvx));
             return;
         }
     }
-    sweep_body<T, TI, true>(a, it, kci, smem, j, B);
+    sweep_body<T, TI, true, BGK>(a, it, kci, smem, j, B);
 }
 
 // Tiles of a launch: blockIdx -> (x chunk, entry of the launch's v_x tile
 // list), remapped so each XCD takes a contiguous range.
-template <typename T, int TI, int MAXB>
+// BGK: compiled with the collision term (a kernel of its own, so the
+// register budget of the plain sweep does not carry it).
+template <typename T, int TI, int MAXB, bool BGK = false>
 __global__ void __launch_bounds__(MAXB) k_sweep(SweepArgs<T> a)
 {
     extern __shared__ double smem[];
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
     const int it = a.tile_list[wg % a.n_list];
-    sweep_fast_dispatch<T, TI>(a, it, wg / a.n_list, smem, threadIdx.x, blockDim.x);
+    sweep_fast_dispatch<T, TI, BGK>(a, it, wg / a.n_list, smem, threadIdx.x, blockDim.x);
 }
 
-template <typename T, int TI, int MAXB>
+template <typename T, int TI, int MAXB, bool BGK = false>
 __global__ void __launch_bounds__(MAXB) k_sweep_generic(SweepArgs<T> a)
 {
     extern __shared__ double smem[];
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
     const int it = a.tile_list[wg % a.n_list];
-    sweep_rest<T, TI>(a, it, wg / a.n_list, smem, threadIdx.x, blockDim.x);
+    sweep_rest<T, TI, BGK>(a, it, wg / a.n_list, smem, threadIdx.x, blockDim.x);
 }
 
 // A sub-tile slot of a batched workgroup with no tile: take part in the same

@@ -58,7 +58,10 @@ def bad(**kw):
 @pytest.mark.parametrize("kw,code", [
     (dict(nx=0), fk.E_INVALID), (dict(nvy=1025), fk.E_INVALID), (dict(length=-1.0), fk.E_INVALID),
     (dict(t_se_ev=0.0), fk.E_INVALID), (dict(x_src_lo=2e-5, x_src_hi=1e-5), fk.E_INVALID),
-    (dict(physics_mask=64), fk.E_INVALID), (dict(emission_norm=2), fk.E_INVALID),
+    (dict(physics_mask=128), fk.E_INVALID), (dict(emission_norm=2), fk.E_INVALID),
+    (dict(physics_mask=W.ALL | W.BGK, t_e_ev=0.0), fk.E_INVALID),
+    (dict(physics_mask=W.BGK, ln_lambda=0.0), fk.E_INVALID),
+    (dict(physics_mask=W.BGK, t_e_ev=float("inf")), fk.E_INVALID),
     (dict(tile_rows=3), fk.E_INVALID), (dict(trace_cap=0), fk.E_INVALID),
     (dict(dt=1e-11), fk.E_CFL), (dict(ey=-1e9, dt=3e-13), fk.E_CFL),
 ])
@@ -124,11 +127,13 @@ def test_saturation_check():
 
 
 def test_batch_rejects_before_touching_the_gpu():
-    """Batched instances are FP32 with nvy <= 256 and the mode is 0 .. 3;
+    """Batched instances are FP32 with nvy <= 256 and no collision term, and
+    the mode is 0 .. 3;
     these are checked on the host before any device call."""
     good = W.config(nx=16, nvx=16, nvy=64, length=1e-3, ey=-5e6, delta_max=2.5, a_max_ev=400.0)
     wide = dict(good, nvy=300)
-    for cfgs, dtype in (([good], "f64"), ([good, wide], "f32")):
+    coll = dict(good, physics_mask=W.ALL | W.BGK)
+    for cfgs, dtype in (([good], "f64"), ([good, wide], "f32"), ([good, coll], "f32")):
         arr = (fk.fk_params * len(cfgs))(*[fk.make_params(c, dtype) for c in cfgs])
         h = C.c_void_p()
         assert fk.fk_batch_create(arr, len(cfgs), None, 0, C.byref(h)) == fk.E_INVALID
@@ -138,3 +143,17 @@ def test_batch_rejects_before_touching_the_gpu():
     assert fk.fk_batch_create(arr, 0, None, 0, C.byref(C.c_void_p())) == fk.E_INVALID
     assert fk.fk_batch_create(arr, 1, None, 4, C.byref(C.c_void_p())) == fk.E_INVALID
     assert fk.fk_batch_create(arr, 1, None, -1, C.byref(C.c_void_p())) == fk.E_INVALID
+
+
+def test_collision_term_is_opt_in_and_costs_lds_only_when_on():
+    """The BGK bit is valid with a temperature and Coulomb logarithm; the
+    parameters are ignored without it, and its per-wave coefficient table
+    is the only change to the launch shape."""
+    cfg = W.c1()
+    plain = fk.validate(fk.make_params(dict(cfg, t_e_ev=0.0, ln_lambda=0.0), "f32"))
+    on = fk.validate(fk.make_params(dict(cfg, physics_mask=W.ALL | W.BGK), "f32"))
+    assert plain["tile_rows"] == on["tile_rows"] and plain["block"] == on["block"]
+    assert on["bytes_device"] == plain["bytes_device"]
+    # the widest FP32 tiles still fit with the larger table
+    wide = fk.validate(fk.make_params(dict(W.c4(), physics_mask=W.ALL | W.BGK), "f32"))
+    assert wide["tile_rows"] == 12
