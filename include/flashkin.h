@@ -227,6 +227,30 @@ int fk_saturated(fk_ctx* ctx, double window_s, double rtol, int* out);
 /* The same test on a caller-held trace (host only, no GPU). */
 int fk_saturation_check(const fk_state* trace, size_t n, double window_s, double rtol, int* out);
 
+/* Field-emission current density at the cathode triple junction, Eq 6
+ * (Fowler-Nordheim), with the work function e*phi_m = phi_ev electron-volts
+ * and the junction field E = beta * |e_field| (Section 2 takes E_CTJ = |E_y|,
+ * i.e. beta = 1; beta > 1 stands for a local field enhancement).  Host only.
+ * *j_out in A/m^2, the rate j_src of the Eq 7 band source; 0 where the
+ * exponential underflows (|E_y| of a few MV/m with beta = 1).
+ * FK_E_INVALID for phi_ev <= 0, beta <= 0, a non-finite field or NULL out. */
+int fk_fn_current(double e_field, double phi_ev, double beta, double* j_out);
+
+/* Surface charge along the insulator from the trace of one 1D element (a
+ * reading of Section 4's comparison, where the 2D charging time is the
+ * insulator length over the avalanche speed v_seea): the avalanche front
+ * leaves the junction (y = 0) at t = 0 and moves at v_seea, and an element
+ * at y charges as the 1D run did from the moment the front reached it:
+ *   sigma(y, t) = sigma_1D(t - y / v_seea),
+ * linear between trace records (sigma + sigma_lo) and from 0 at the front
+ * to the first record (the run starts uncharged, Section 2), 0 ahead of
+ * the front (y > v_seea t) and the last record's value past the trace.
+ * Host only.  trace: n >= 1 records in increasing t; y: ny positions (m);
+ * out: ny values (C/m^2).  FK_E_INVALID for v_seea <= 0, NULL arrays with
+ * n or ny > 0, or records out of order. */
+int fk_sigma_along(const fk_state* trace, size_t n, double v_seea, double t, const double* y, size_t ny,
+                   double* out);
+
 /* Kernel timing.  fk_set_profiling(ctx, every) with every >= 1 switches
  * profiling on: fk_step then launches every step directly (no graphs) and,
  * for every `every`-th step counted from the call (the first included),

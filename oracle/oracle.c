@@ -126,6 +126,20 @@ double orc_sey(double delta_max, double a_max_ev, double ks, double a_in_ev, dou
          * -expm1(-pow(z, 1.725)) / pow(z, 0.725);   /* 1 - exp(-z^1.725) */
 }
 
+/* ---- field-emission current density, Eq 6 ----------------------------
+   e_field in V/m (its magnitude times beta is the junction field), phi_ev
+   the work function in eV; the result is in A/m^2. */
+#define ORC_PLANCK 6.62607015e-34   /* J s */
+double orc_fn_current(double e_field, double phi_ev, double beta)
+{
+    double E = beta * fabs(e_field);
+    double phi = phi_ev * ORC_E;
+    if (E == 0.0) return 0.0;
+    double a = pow(ORC_E, 3) * E * E / (8.0 * ORC_PI * ORC_PLANCK * phi);
+    double expo = 8.0 * ORC_PI * sqrt(2.0 * ORC_ME * pow(phi, 3)) / (3.0 * ORC_E * ORC_PLANCK * E);
+    return a * exp(-expo);
+}
+
 /* ---- electron-electron collision frequency, Eq 4 ----------------------
    n_e in 1/m^3, T_e in eV (converted to joules); the result is in 1/s. */
 double orc_nu_ee(double n_e, double t_e_ev, double ln_lambda)

@@ -71,6 +71,8 @@ def lib():
         L.orc_cfl_max_vx.argtypes = [C.c_void_p]
         L.orc_sey.restype = C.c_double
         L.orc_sey.argtypes = [C.c_double] * 5
+        L.orc_fn_current.restype = C.c_double
+        L.orc_fn_current.argtypes = [C.c_double] * 3
         L.orc_nu_ee.restype = C.c_double
         L.orc_nu_ee.argtypes = [C.c_double] * 3
         L.orc_nu_dt_max.restype = C.c_double
@@ -87,6 +89,11 @@ def _ptr(a):
 def sey(delta_max, a_max_ev, ks, a_in_ev, alpha):
     """Eq 8-9 evaluated by the C oracle at one (energy, angle)."""
     return lib().orc_sey(delta_max, a_max_ev, ks, a_in_ev, alpha)
+
+
+def fn_current(e_field, phi_ev, beta=1.0):
+    """Eq 6 evaluated by the C oracle (A/m^2)."""
+    return lib().orc_fn_current(float(e_field), float(phi_ev), float(beta))
 
 
 def nu_ee(n_e, t_e_ev, ln_lambda):

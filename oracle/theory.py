@@ -44,3 +44,20 @@ def flight_time(sigma, a0_ev):
 def primary_flux_saturated(sigma, a0_ev):
     """Flux estimate Gamma_pe = sigma / (e t_ef) (Section 4)."""
     return sigma / (E_CHARGE * flight_time(sigma, a0_ev))
+
+
+def sigma_along(times, sigmas, v_seea, t, y):
+    """Surface charge along the insulator from a 1D trace (a reading of
+    Section 4: the avalanche front moves from the junction at v_seea and
+    each element then charges as the 1D run did): sigma_1D(t - y / v_seea),
+    piecewise linear through (0, 0) and the records, 0 ahead of the front,
+    the last value after the trace ends.  Plain numpy interpolation."""
+    import numpy as np
+    times = np.asarray(times, dtype=np.float64)
+    sigmas = np.asarray(sigmas, dtype=np.float64)
+    tau = t - np.asarray(y, dtype=np.float64) / v_seea
+    if times[0] > 0:
+        times = np.concatenate([[0.0], times])
+        sigmas = np.concatenate([[0.0], sigmas])
+    out = np.interp(tau, times, sigmas, left=0.0, right=sigmas[-1])
+    return np.where(tau < 0, 0.0, out)

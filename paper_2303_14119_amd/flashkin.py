@@ -107,6 +107,9 @@ SIGNATURES = {
     "fk_write_state": (C.c_int, [_ctx, _vp, C.c_int, C.c_double, C.c_double, C.c_int64]),
     "fk_saturated": (C.c_int, [_ctx, C.c_double, C.c_double, _P(C.c_int)]),
     "fk_saturation_check": (C.c_int, [_P(fk_state), C.c_size_t, C.c_double, C.c_double, _P(C.c_int)]),
+    "fk_fn_current": (C.c_int, [C.c_double, C.c_double, C.c_double, _P(C.c_double)]),
+    "fk_sigma_along": (C.c_int, [_P(fk_state), C.c_size_t, C.c_double, C.c_double, _P(C.c_double), C.c_size_t,
+                                 _P(C.c_double)]),
     "fk_set_profiling": (C.c_int, [_ctx, C.c_int]),
     "fk_kernel_times": (C.c_int, [_ctx, _P(C.c_double), _P(C.c_int64), _P(C.c_double), _P(C.c_int64)]),
     "fk_autotune": (C.c_int, [_ctx, C.c_int, _P(fk_info)]),
@@ -185,6 +188,37 @@ def saturation_check(records, window_s, rtol):
     out = C.c_int(0)
     check(fk_saturation_check(arr, len(records), window_s, rtol, C.byref(out)))
     return bool(out.value)
+
+
+def fn_current(e_field, phi_ev, beta=1.0):
+    """Eq 6: field-emission current density (A/m^2) at junction field
+    beta * |e_field| and work function phi_ev (eV)."""
+    out = C.c_double(0.0)
+    check(fk_fn_current(float(e_field), float(phi_ev), float(beta), C.byref(out)))
+    return out.value
+
+
+def _as_states(records):
+    out = (fk_state * len(records))()
+    for m, r in enumerate(records):
+        if isinstance(r, fk_state):
+            out[m] = r
+        else:
+            for name, _ in fk_state._fields_:
+                setattr(out[m], name, r.get(name, 0))
+    return out
+
+
+def sigma_along(records, v_seea, t, y):
+    """sigma(y, t) along the insulator from a 1D trace (fk_sigma_along):
+    records are fk_state or dictionaries of its fields, y positions in m."""
+    arr = _as_states(records)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    out = np.empty_like(y)
+    P = C.POINTER(C.c_double)
+    check(fk_sigma_along(arr, len(records), float(v_seea), float(t), y.ctypes.data_as(P), y.size,
+                         out.ctypes.data_as(P)))
+    return out
 
 
 class Solver:

@@ -93,6 +93,36 @@ def test_bench_workload_random_state(fk):
     assert rel(st["sigma"] + st["sigma_lo"], orc["sigma"]) <= 1e-6
 
 
+def test_bench_workload_with_collisions(fk):
+    """The 2048 x 256 x 256 launch with the collision term (Eq 3-5) on, at
+    densities where nu_ee dt reaches 1e-3 in the densest planes (the self
+    field is replaced by a uniform E_x there, as it would break the v_x
+    Courant limit): FP32 against FP64 after three steps."""
+    from oracle.solver import nu_ee
+    cfg = dict(W.c1(), physics_mask=(W.ALL & ~W.SELF) | W.BGK, ex_external=1e5, t_e_ev=2.0, ln_lambda=10.0)
+    f0 = separable_state((cfg["nx"], cfg["nvx"], cfg["nvy"]), seed=13, scale=1.0)
+    o = Oracle(cfg)
+    dv2 = (2 * cfg["vmax_x"] / cfg["nvx"]) * (2 * cfg["vmax_y"] / cfg["nvy"])
+    dens = f0.sum(axis=(1, 2), dtype=np.float64) * dv2
+    f0 *= np.float32(1e-3 / (nu_ee(dens.max(), 2.0, 10.0) * o.dt))
+    o.set_state(f0.astype(np.float64), 4e-6, 0)
+    o.step(3)
+    assert o.nu_dt_max() > 9e-4
+    with fk.Solver(cfg, "f32") as s:
+        s.write_state(f0, 4e-6, 0.0, 0)
+        s.step(3)
+        s.sync()
+        g, st = s.f(), s.state()
+    ref, orc = o.f(), o.record()
+    o.close()
+    err = rel_l2(g, ref)
+    print("2048x256x256 with collisions, 3 steps: f", err)
+    assert err <= 1e-6
+    for q in ("g_pe", "g_see", "g_top", "n_total"):
+        assert rel(st[q], orc[q]) <= 1e-6, q
+    assert rel(st["sigma"] + st["sigma_lo"], orc["sigma"]) <= 1e-6
+
+
 def test_large_grid_two_steps(fk):
     """4096 x 384 x 384 (604M cells, 2.4 GB per f buffer)."""
     cfg = W.c4()
