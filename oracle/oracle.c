@@ -19,6 +19,9 @@
  *   - the SEE yield matrix (Eq 8-11), the primary and secondary wall fluxes
  *     (Eq 12-14), the half-Maxwellian emission boundary (Eq 15-16), the
  *     absorbing vacuum boundary (Eq 17) and the surface-charge update (Eq 18);
+ *   - optionally a wall reflection coefficient R_f (Section 2, after Eq 14):
+ *     a fraction R_f of the electrons reaching the wall is reflected
+ *     specularly (v_x -> -v_x) into the emission row, the rest induces SEE;
  *   - optionally (ORC_BGK) the electron-electron collision term: relaxation
  *     towards the Maxwellian of Eq 5 at T_e, at the frequency of Eq 4
  *     (Eq 3), evaluated on f^n and n^n and added after the source.
@@ -75,6 +78,7 @@ typedef struct {
     double ex_external;     /* uniform E_x added to the self field, V/m */
     double t_e_ev;          /* temperature of the collisional equilibrium (Eq 4-5), eV */
     double ln_lambda;       /* Coulomb logarithm of Eq 4 */
+    double r_refl;          /* wall reflection coefficient R_f (Section 2, after Eq 14), 0..1 */
 } orc_params;
 
 /* The observables of the state (f^n, sigma^n) after n steps. */
@@ -83,7 +87,7 @@ typedef struct {
     double t;
     double sigma;     /* sigma^n, C/m^2 */
     double g_pe;      /* primary flux into the wall from f^n, Eq 13-14, 1/(m^2 s) */
-    double g_see;     /* secondary flux, Eq 12-14 */
+    double g_see;     /* secondary flux, Eq 12-14 (times 1 - R_f) */
     double g_top;     /* flux leaving through the vacuum boundary from f^n */
     double emitted;   /* flux carried by the emission ghost row, sum v_x g dv^2 */
     double loss_v;    /* electrons/m^2 lost through the velocity-box edges in step n-1 */
@@ -262,6 +266,9 @@ static orc_moments prologue(orc_sim* s)
         }
     }
 
+    /* only the fraction 1 - R_f of the arriving electrons induces SEE */
+    mo.g_see *= 1.0 - p->r_refl;
+
     /* Eq 15: emission boundary row at x = 0 for v_x > 0 */
     double coef;
     if (p->emission_norm == 0)
@@ -274,6 +281,10 @@ static orc_moments prologue(orc_sim* s)
         for (int j = 0; j < p->nvy; ++j) {
             size_t m = (size_t)i * p->nvy + j;
             s->ghost[m] = coef * s->ghat[m];
+            /* specular reflection: the wall cell's electrons at -v_x come
+               back at +v_x (cell nvx-1-i holds -v_x of cell i) */
+            if (s->vx[i] > 0.0 && p->r_refl > 0.0)
+                s->ghost[m] += p->r_refl * s->f[idx(s, 0, p->nvx - 1 - i, j)];
             if (s->vx[i] > 0.0) mo.emitted += s->vx[i] * s->ghost[m] * dv2;
         }
     if (!(p->physics_mask & ORC_X)) mo.emitted = 0.0;
@@ -520,8 +531,10 @@ void orc_step(orc_sim* s, int64_t n, orc_record* trace)
     for (int64_t it = 0; it < n; ++it) {
         orc_moments mo = prologue(s);
 
-        /* Eq 18: the surface charge of the next step */
-        double sigma_next = s->sigma + ORC_E * s->dt * (mo.g_see - mo.g_pe);
+        /* Eq 18: the surface charge of the next step; reflected electrons
+           leave the wall again and deposit no charge */
+        double g_refl = (p->physics_mask & ORC_X) ? p->r_refl * mo.g_pe : 0.0;
+        double sigma_next = s->sigma + ORC_E * s->dt * (mo.g_see + g_refl - mo.g_pe);
 
         for (int k = 0; k < p->nx; ++k) {
             double d = fabs(-ORC_E * s->ex[k] / ORC_ME * s->dt / s->dvx);

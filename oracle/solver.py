@@ -29,6 +29,7 @@ class _Params(C.Structure):
         ("x_src_hi", C.c_double), ("t_src_ev", C.c_double),
         ("emission_norm", C.c_int), ("physics_mask", C.c_uint),
         ("ex_external", C.c_double), ("t_e_ev", C.c_double), ("ln_lambda", C.c_double),
+        ("r_refl", C.c_double),
     ]
 
 

@@ -19,6 +19,7 @@ Parameter keys (SI units unless the name says eV):
   ex_external              uniform E_x added to the self field
   t_e_ev, ln_lambda        temperature and Coulomb logarithm of the electron-
                            electron collision term (Eq 3-5), used with BGK
+  r_refl                   wall reflection coefficient R_f (0: none)
 """
 import math
 
@@ -42,7 +43,7 @@ VMAX_1KEV = speed_of(1000.0)
 
 _BASE = dict(
     dt=0.0, cfl=0.9, ks=1.0, t_se_ev=2.0, j_src=1.0e5, x_src_lo=10e-6, x_src_hi=15e-6,
-    t_src_ev=2.0, emission_norm=0, physics_mask=ALL, ex_external=0.0, t_e_ev=2.0, ln_lambda=10.0,
+    t_src_ev=2.0, emission_norm=0, physics_mask=ALL, ex_external=0.0, t_e_ev=2.0, ln_lambda=10.0, r_refl=0.0,
     vmax_x=VMAX_1KEV, vmax_y=VMAX_1KEV,
 )
 
