@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define FK_ABI_VERSION 3u   /* 2: fk_batch_info_t gained single_threads; 3: fk_params gained t_e_ev, ln_lambda */
+#define FK_ABI_VERSION 4u   /* 2: fk_batch_info_t gained single_threads; 3: fk_params gained t_e_ev, ln_lambda; 4: r_refl */
 
 /* element type of f */
 enum { FK_F32 = 0, FK_F64 = 1 };
@@ -106,6 +106,10 @@ typedef struct {
     int32_t tile_planes;     /* x planes per tile; 0: chosen at creation from the sweep kernel's occupancy: the longest run (16..128) that keeps 8 waves resident per compute unit, or all a unit holds, with the workgroups spread evenly (fk_validate reports a host-side estimate, fk_query the choice); batch instances get 16 */
     double t_e_ev;           /* FK_PHYS_BGK: temperature of the collisional equilibrium (Eq 4-5), eV, > 0 */
     double ln_lambda;        /* FK_PHYS_BGK: Coulomb logarithm of Eq 4 (the paper: 10), > 0 */
+    double r_refl;           /* wall reflection coefficient R_f in [0, 1] (Section 2, after Eq 14): a fraction
+                              * R_f of the electrons reaching the dielectric returns specularly (v_x -> -v_x)
+                              * through the emission row, 1 - R_f induces SEE (Gamma_see scales by 1 - R_f),
+                              * and reflected electrons deposit no charge in Eq 18.  0: no reflection */
 } fk_params;
 
 /* Observables of the state (f^n, sigma^n) after n steps.  The fluxes are
@@ -116,9 +120,9 @@ typedef struct {
     double sigma;            /* surface charge sigma^n, C/m^2 (Eq 18) */
     double sigma_lo;         /* compensation term of the sigma sum (sigma + sigma_lo is the value) */
     double g_pe;             /* primary flux into the wall, 1/(m^2 s) (Eq 13-14) */
-    double g_see;            /* secondary flux (Eq 12, 14) */
+    double g_see;            /* secondary flux (Eq 12, 14), times 1 - r_refl */
     double g_top;            /* flux leaving through x = L */
-    double emitted;          /* flux carried by the emission row, sum v_x f_ghost dv_x dv_y */
+    double emitted;          /* flux carried by the emission row, sum v_x f_ghost dv_x dv_y (secondaries plus reflected) */
     double loss_v;           /* electrons/m^2 lost through the velocity-box edges in step n */
     double n_total;          /* electrons/m^2 in the domain */
     double resid;            /* particle balance residual of step n, electrons/m^2 */

@@ -52,6 +52,7 @@ int derive_layout(const fk_params* p, Layout* L, std::string* why)
     const bool bgk = (p->physics_mask & FK_PHYS_BGK) != 0;
     if (bgk && !(p->t_e_ev > 0 && std::isfinite(p->t_e_ev))) return bad("t_e_ev must be > 0 and finite with FK_PHYS_BGK");
     if (bgk && !(p->ln_lambda > 0 && std::isfinite(p->ln_lambda))) return bad("ln_lambda must be > 0 and finite with FK_PHYS_BGK");
+    if (!(p->r_refl >= 0 && p->r_refl <= 1)) return bad("r_refl must be in [0, 1]");
     if (p->trace_stride < 1 || p->trace_cap < 1) return bad("trace_stride and trace_cap must be >= 1");
     if (p->tile_rows != 0 && p->tile_rows != 4 && p->tile_rows != 8 && p->tile_rows != 12 && p->tile_rows != 16)
         return bad("tile_rows must be 0, 4, 8, 12 or 16");

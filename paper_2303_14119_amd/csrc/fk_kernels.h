@@ -136,6 +136,7 @@ struct SweepArgs {
     int nx, nvx, nvy, n_it, kc;
     double dvx, dt_dx;                  // v_x of row i is cell_v(i, nvx, dvx)
     double dy;                          // signed v_y Courant number
+    double r_refl;                      // wall reflection: share of the wall cell's -v_x electrons returned at +v_x
     int x_on;
     int store_nt;                       // 1: stores of f^{n+1} are non-temporal (whole 128 B lines per row)
     const int* __restrict__ tile_list;  // v_x tile indices handled by this launch
@@ -246,7 +247,14 @@ __device__ __forceinline__ void sweep_body(const SweepArgs<T>& a, int it, int kc
 #pragma unroll
         for (int r = 0; r < TI + 2; ++r) {
             const int i = i0 - 1 + r;
-            fm[r] = (rv[r] && up_row(r) && jok) ? T(gs * a.ghat[(size_t)i * a.nvy + j]) : T(0);
+            // plus the specular reflection of the wall cell (v_x row nvx-1-i
+            // holds -v_x of row i)
+            double g = 0.0;
+            if (rv[r] && up_row(r) && jok) {
+                g = gs * a.ghat[(size_t)i * a.nvy + j];
+                if (a.r_refl != 0.0) g += a.r_refl * (double)a.fin[(size_t)(a.nvx - 1 - i) * a.nvy + j];
+            }
+            fm[r] = T(g);
         }
     } else {
         const rsrc_t pr = plane_in(k0 - 1);
@@ -546,6 +554,7 @@ struct FieldArgs {
     int emission_norm, trace_stride, trace_cap;
     double dx, dv2, dt, dvx, ex_ext;
     double nudt_per_n;              // dt nu_ee / n_e of Eq 4 (0: no collision term)
+    double r_refl;                  // wall reflection coefficient R_f
 };
 
 // Reduction of the moment partials of the new f over the v_x tiles (fixed
@@ -666,7 +675,8 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
     double sig = old.sigma, sig_lo = old.sigma_lo;
     if (a.advance) {
         // Eq 18 with the fluxes of f^n, Neumaier-compensated across steps
-        const double inc = kE * a.dt * (old.g_see - old.g_pe);
+        // reflected electrons (r_refl g_pe) leave the wall again
+        const double inc = kE * a.dt * (old.g_see + a.r_refl * old.g_pe - old.g_pe);
         const double s = sig + inc;
         if (fabs(sig) >= fabs(inc)) sig_lo += (sig - s) + inc;
         else sig_lo += (inc - s) + sig;
@@ -727,14 +737,14 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
         const bool x_on = a.mask & FK_PHYS_X;
         const bool see_on = x_on && (a.mask & FK_PHYS_SEE);
         const double g_pe = x_on ? pe * a.dv2 : 0.0;
-        const double g_see = see_on ? see * a.dv2 : 0.0;
+        const double g_see = see_on ? see * a.dv2 * (1.0 - a.r_refl) : 0.0;   // 1 - R_f of the arrivals induce SEE
         const double g_top = x_on ? top * a.dv2 : 0.0;
         double gscale = 0.0;
         if (see_on) {
             if (a.emission_norm == FK_EMIT_DISCRETE) gscale = zsum > 0.0 ? g_see / zsum : 0.0;
             else gscale = g_see * emit_pref;
         }
-        const double emitted = gscale * zsum;
+        const double emitted = gscale * zsum + (x_on ? a.r_refl * g_pe : 0.0);
         const double n_total = total * a.dx;
         const double loss_v = a.advance ? lv * a.dx * a.dv2 : 0.0;
         double resid = 0.0;

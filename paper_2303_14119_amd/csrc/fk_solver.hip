@@ -303,6 +303,7 @@ SweepArgs<T> sweep_args(const fk_ctx* c, int from)
     a.dvx = c->L.dvx;
     a.dt_dx = c->L.dt / c->L.dx;
     a.dy = c->L.dy;
+    a.r_refl = c->p.r_refl;
     a.x_on = (c->p.physics_mask & FK_PHYS_X) ? 1 : 0;
     // non-temporal stores pay when every row of f starts on a 128-byte line,
     // so that each wave writes whole lines; a row that shares lines with its
@@ -406,6 +407,7 @@ FieldArgs field_args(const fk_ctx* c, int advance)
     a.dt = c->L.dt;
     a.dvx = c->L.dvx;
     a.ex_ext = c->p.ex_external;
+    a.r_refl = c->p.r_refl;
     if (c->L.bgk) {
         // Eq 4: nu_ee = n_e e^4 ln(Lambda) / (12 pi^1.5 eps0^2 sqrt(m_e) T_e^1.5), T_e in joules
         const double te = c->p.t_e_ev * kE;

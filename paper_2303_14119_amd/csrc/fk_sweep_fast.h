@@ -95,7 +95,14 @@ __device__ __forceinline__ void sweep_fast(const SweepArgs<T>& a, int it, int kc
 #pragma unroll
             for (int r = S; r < TI + 2; ++r) {
                 const int i = i0 - 1 + r;
-                w0[r] = (jok && i < a.nvx) ? T(gs * a.ghat[(size_t)i * a.nvy + j]) : T(0);
+                // plus the specular reflection of the wall cell (v_x row
+                // nvx-1-i holds -v_x of row i)
+                double g = 0.0;
+                if (jok && i < a.nvx) {
+                    g = gs * a.ghat[(size_t)i * a.nvy + j];
+                    if (a.r_refl != 0.0) g += a.r_refl * (double)a.fin[(size_t)(a.nvx - 1 - i) * a.nvy + j];
+                }
+                w0[r] = T(g);
             }
         } else {
             const rsrc_t pd = plane_in(k0 - 1);

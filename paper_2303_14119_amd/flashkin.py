@@ -27,7 +27,7 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2303_14119_amd.build`")
 _lib = C.CDLL(LIB_PATH)
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 F32, F64 = 0, 1
 EMIT_DISCRETE, EMIT_ANALYTIC = 0, 1
 PHYS_X, PHYS_VX, PHYS_VY, PHYS_SRC, PHYS_SEE, PHYS_SELF_FIELD, PHYS_ALL = 1, 2, 4, 8, 16, 32, 63
@@ -47,7 +47,7 @@ class fk_params(C.Structure):
         ("emission_norm", C.c_int32), ("physics_mask", C.c_uint32),
         ("ex_external", C.c_double), ("trace_stride", C.c_int32), ("trace_cap", C.c_int32),
         ("tile_rows", C.c_int32), ("tile_planes", C.c_int32),
-        ("t_e_ev", C.c_double), ("ln_lambda", C.c_double),
+        ("t_e_ev", C.c_double), ("ln_lambda", C.c_double), ("r_refl", C.c_double),
     ]
 
 
@@ -157,9 +157,9 @@ def check(code, ctx=None):
 
 PARAM_KEYS = ("nx", "nvx", "nvy", "length", "vmax_x", "vmax_y", "dt", "cfl", "ey", "delta_max",
               "a_max_ev", "ks", "t_se_ev", "j_src", "x_src_lo", "x_src_hi", "t_src_ev",
-              "emission_norm", "physics_mask", "ex_external", "t_e_ev", "ln_lambda")
+              "emission_norm", "physics_mask", "ex_external", "t_e_ev", "ln_lambda", "r_refl")
 # keys a dictionary may leave out (used only with PHYS_BGK): the paper's values
-OPTIONAL_KEYS = {"t_e_ev": 2.0, "ln_lambda": 10.0}
+OPTIONAL_KEYS = {"t_e_ev": 2.0, "ln_lambda": 10.0, "r_refl": 0.0}
 
 
 def make_params(cfg, dtype="f32", trace_stride=1, trace_cap=4096, tile_rows=0, tile_planes=0):

@@ -62,6 +62,7 @@ def bad(**kw):
     (dict(physics_mask=W.ALL | W.BGK, t_e_ev=0.0), fk.E_INVALID),
     (dict(physics_mask=W.BGK, ln_lambda=0.0), fk.E_INVALID),
     (dict(physics_mask=W.BGK, t_e_ev=float("inf")), fk.E_INVALID),
+    (dict(r_refl=-0.1), fk.E_INVALID), (dict(r_refl=1.5), fk.E_INVALID), (dict(r_refl=float("nan")), fk.E_INVALID),
     (dict(tile_rows=3), fk.E_INVALID), (dict(trace_cap=0), fk.E_INVALID),
     (dict(dt=1e-11), fk.E_CFL), (dict(ey=-1e9, dt=3e-13), fk.E_CFL),
 ])
