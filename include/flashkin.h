@@ -62,7 +62,7 @@ enum {
      * nu_ee(n_e) of Eq 4 with ln_lambda.  Opt-in (not part of FK_PHYS_ALL).
      * Taken explicitly on f^n and n^n and added to the swept f; the
      * Maxwellian is normalised on the grid, so the term moves no electrons
-     * between x planes.  Single contexts only (fk_batch_create rejects it). */
+     * between x planes. */
     FK_PHYS_BGK = 64
 };
 
@@ -282,7 +282,9 @@ int fk_autotune(fk_ctx* ctx, int trial_steps, fk_info* chosen);
  * x chunk, v_x tiles) work items largest first from an atomic counter; one
  * field launch then reduces and solves every instance (a workgroup each);
  * steps are replayed from HIP graphs.  Every instance is FK_F32 with
- * nvy <= 256, without FK_PHYS_BGK, and starts at f = 0, sigma = 0.
+ * nvy <= 256 and starts at f = 0, sigma = 0.  If any member has
+ * FK_PHYS_BGK the batch runs the sweep variant with the collision term
+ * (members without it skip the term).
  *   mode 0: split launches: up to four sweep launches per step, by tile
  *           body and workgroup width;
  *   mode 1: autotune: time short trial runs of tilings, grid sizes, item

@@ -1166,9 +1166,12 @@ struct BatchItem {
 // w takes items w, w + grid, ... of the cost-sorted list (static).  The
 // launch bound asks for 4 workgroups of 256 threads per compute unit, i.e.
 // at most 128 VGPRs: the kernels that carry the generic body then keep 4
-// waves per SIMD instead of 3 (131 -> 127 VGPRs, no spills).
-template <int TI, int BODY>
-__global__ void __launch_bounds__(kBatchThreads, 4) k_batch_sweep(const BatchInst* __restrict__ insts,
+// waves per SIMD instead of 3 (131 -> 127 VGPRs, no spills).  BGK: the
+// variant with the collision term (any member has it; members without it
+// have zero coefficients and skip it), bounded at 2 workgroups per unit so
+// its larger bodies do not spill.
+template <int TI, int BODY, bool BGK = false>
+__global__ void __launch_bounds__(kBatchThreads, BGK ? 2 : 4) k_batch_sweep(const BatchInst* __restrict__ insts,
                                                                const BatchItem* __restrict__ items,
                                                                int n_items, int* __restrict__ counter, int from,
                                                                int sched)
@@ -1199,9 +1202,9 @@ __global__ void __launch_bounds__(kBatchThreads, 4) k_batch_sweep(const BatchIns
             double* slot = smem + (size_t)sub * in->lds_doubles;
             const SweepArgs<float>& a = in->sw[from];
             if (BODY == BODY_FAST || (BODY == BODY_ANY && tile_is_fast(it, TI, a.nvx)))
-                sweep_fast_dispatch<float, TI>(a, it, kci, slot, j, B);
+                sweep_fast_dispatch<float, TI, BGK>(a, it, kci, slot, j, B);
             else
-                sweep_rest<float, TI>(a, it, kci, slot, j, B);
+                sweep_rest<float, TI, BGK>(a, it, kci, slot, j, B);
         } else {
             sweep_idle(np);
         }
@@ -1227,6 +1230,7 @@ struct fk_batch {
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
     int ti = 8;
+    int bgk = 0;                  // 1: a member has the collision term (the sweep variant with it)
     int sched = 0;                // 0 dynamic (atomic counter), 1 static round-robin
     int single = 0;               // 1: one sweep launch per step (class 4 only)
     int single_width = 0;         // threads per workgroup of that launch asked for: 192, or 0 (256)
@@ -1262,16 +1266,14 @@ int bfail(fk_batch* b, hipError_t e, const char* what)
         if (e_ != hipSuccess) return bfail((b), e_, #call);  \
     } while (0)
 
-size_t batch_slice_doubles(int ti, int block, int kc)
+size_t batch_slice_doubles(int ti, int block, int kc, bool bgk)
 {
-    const int waves = block / 64;
-    const size_t bytes = (size_t)2 * ti * (block + 2) * 4 + (size_t)kc * waves * 8 + (size_t)waves * 32 + (size_t)waves * 2 * kc * 4;
-    return (bytes + 7) / 8;
+    return (sweep_lds(ti, block, kc, 4, bgk) + 7) / 8;
 }
 
 int batch_threads(const fk_batch* b, int k) { return k == 4 ? b->single_threads : class_threads(k); }
 
-template <int TI>
+template <int TI, bool BGK>
 void batch_launch_sweeps(const fk_batch* b, int from, hipStream_t s)
 {
     for (int k = 0; k < kBatchClasses; ++k) {
@@ -1281,16 +1283,16 @@ void batch_launch_sweeps(const fk_batch* b, int from, hipStream_t s)
         int* ctr = b->d_counter + k;
         switch (class_body(k)) {
         case BODY_FAST:
-            hipLaunchKernelGGL((k_batch_sweep<TI, BODY_FAST>), grid, block, b->lds, s, b->d_inst, items, b->cls_n[k],
-                               ctr, from, b->sched);
+            hipLaunchKernelGGL((k_batch_sweep<TI, BODY_FAST, BGK>), grid, block, b->lds, s, b->d_inst, items,
+                               b->cls_n[k], ctr, from, b->sched);
             break;
         case BODY_REST:
-            hipLaunchKernelGGL((k_batch_sweep<TI, BODY_REST>), grid, block, b->lds, s, b->d_inst, items, b->cls_n[k],
-                               ctr, from, b->sched);
+            hipLaunchKernelGGL((k_batch_sweep<TI, BODY_REST, BGK>), grid, block, b->lds, s, b->d_inst, items,
+                               b->cls_n[k], ctr, from, b->sched);
             break;
         default:
-            hipLaunchKernelGGL((k_batch_sweep<TI, BODY_ANY>), grid, block, b->lds, s, b->d_inst, items, b->cls_n[k],
-                               ctr, from, b->sched);
+            hipLaunchKernelGGL((k_batch_sweep<TI, BODY_ANY, BGK>), grid, block, b->lds, s, b->d_inst, items,
+                               b->cls_n[k], ctr, from, b->sched);
             break;
         }
     }
@@ -1298,24 +1300,31 @@ void batch_launch_sweeps(const fk_batch* b, int from, hipStream_t s)
 
 void batch_launch_step(const fk_batch* b, int from, hipStream_t s)
 {
-    if (b->ti == 4) batch_launch_sweeps<4>(b, from, s);
-    else batch_launch_sweeps<8>(b, from, s);
+    if (b->bgk) {
+        if (b->ti == 4) batch_launch_sweeps<4, true>(b, from, s);
+        else batch_launch_sweeps<8, true>(b, from, s);
+    } else {
+        if (b->ti == 4) batch_launch_sweeps<4, false>(b, from, s);
+        else batch_launch_sweeps<8, false>(b, from, s);
+    }
     hipLaunchKernelGGL(k_batch_field, dim3(b->n_active), dim3(kFieldThreads), 0, s, b->d_inst, b->d_counter, 1);
 }
 
-template <int TI>
+template <int TI, bool BGK>
 hipError_t batch_occupancy_t(int k, int nt, size_t lds, int* occ)
 {
     switch (class_body(k)) {
-    case BODY_FAST: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_batch_sweep<TI, BODY_FAST>, nt, lds);
-    case BODY_REST: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_batch_sweep<TI, BODY_REST>, nt, lds);
-    default: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_batch_sweep<TI, BODY_ANY>, nt, lds);
+    case BODY_FAST: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_batch_sweep<TI, BODY_FAST, BGK>, nt, lds);
+    case BODY_REST: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_batch_sweep<TI, BODY_REST, BGK>, nt, lds);
+    default: return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k_batch_sweep<TI, BODY_ANY, BGK>, nt, lds);
     }
 }
 
-int batch_occupancy(int ti, int k, int nt, size_t lds, int* occ)
+int batch_occupancy(int ti, bool bgk, int k, int nt, size_t lds, int* occ)
 {
-    const hipError_t e = ti == 4 ? batch_occupancy_t<4>(k, nt, lds, occ) : batch_occupancy_t<8>(k, nt, lds, occ);
+    hipError_t e;
+    if (bgk) e = ti == 4 ? batch_occupancy_t<4, true>(k, nt, lds, occ) : batch_occupancy_t<8, true>(k, nt, lds, occ);
+    else e = ti == 4 ? batch_occupancy_t<4, false>(k, nt, lds, occ) : batch_occupancy_t<8, false>(k, nt, lds, occ);
     return e == hipSuccess ? FK_OK : FK_E_HIP;
 }
 
@@ -1357,7 +1366,7 @@ int batch_build(fk_batch* b, int wgs_per_cu)
         d.group = b->single ? b->single_threads / c->L.block : std::min(kBatchMaxGroup, kBatchThreads / c->L.block);
         d.kc = c->L.kc;
         d.nx = c->p.nx;
-        d.lds_doubles = (int)batch_slice_doubles(b->ti, c->L.block, c->L.kc);
+        d.lds_doubles = (int)batch_slice_doubles(b->ti, c->L.block, c->L.kc, b->bgk != 0);
         b->lds = std::max(b->lds, (size_t)d.group * d.lds_doubles * 8);
         b->inst_host.push_back(d);
         // tiles by body, in groups of d.group for every x chunk
@@ -1423,7 +1432,7 @@ int batch_build(fk_batch* b, int wgs_per_cu)
     for (int k = 0; k < kBatchClasses; ++k) {
         if (b->cls_n[k] == 0) continue;
         int occ = 0;
-        if (batch_occupancy(b->ti, k, batch_threads(b, k), b->lds, &occ))
+        if (batch_occupancy(b->ti, b->bgk != 0, k, batch_threads(b, k), b->lds, &occ))
             return set_error(&b->err, FK_E_HIP, "hipOccupancyMaxActiveBlocksPerMultiprocessor failed");
         if (occ < 1) return set_error(&b->err, FK_E_INVALID, "batch tiles need more LDS than a compute unit has");
         // the fast classes carry the bulk: they take the tuned occupancy
@@ -1511,8 +1520,6 @@ extern "C" int fk_batch_create(const fk_params* params, int n, void* stream, int
         int rc = derive_layout(&params[m], &L, &why);
         if (rc) return set_error(nullptr, rc, "instance " + std::to_string(m) + ": " + why);
         if (params[m].dtype != FK_F32) return set_error(nullptr, FK_E_INVALID, "batched instances are FK_F32");
-        if (params[m].physics_mask & FK_PHYS_BGK)
-            return set_error(nullptr, FK_E_INVALID, "batched instances do not take the collision term (FK_PHYS_BGK)");
         if (L.block > kBatchThreads) return set_error(nullptr, FK_E_INVALID, "batched instances need nvy <= 256");
     }
     fk_batch* b = new (std::nothrow) fk_batch();
@@ -1524,6 +1531,8 @@ extern "C" int fk_batch_create(const fk_params* params, int n, void* stream, int
     }
     b->single = mode >= 2 ? 1 : 0;
     b->single_width = mode == 3 ? 192 : 0;
+    for (int m = 0; m < n; ++m)
+        if (params[m].physics_mask & FK_PHYS_BGK) b->bgk = 1;
     int rc = FK_OK;
     hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) rc = bfail(b, e, "hipStreamCreateWithFlags");

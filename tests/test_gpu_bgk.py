@@ -163,8 +163,32 @@ def test_relaxation_number_above_one_is_flagged(fk):
         s.sync()
 
 
-def test_batch_rejects_the_collision_term(fk):
-    good = W.config(nx=16, nvx=16, nvy=64, length=1e-3, ey=-5e6, delta_max=2.5, a_max_ev=400.0)
-    with pytest.raises(fk.FlashkinError) as e:
-        fk.Batch([good, dict(good, physics_mask=W.ALL | W.BGK)])
-    assert e.value.code == fk.E_INVALID
+def test_collisions_in_a_batch(fk):
+    """Batch members with and without the term against the oracle (the
+    batch runs the sweep variant with it; members without it skip it)."""
+    rng = np.random.default_rng(31)
+    cfgs, states = [], []
+    for m in range(4):
+        nv = int(rng.integers(24, 200))
+        mask = (W.ALL & ~W.SELF) | (W.BGK if m != 1 else 0)
+        c = W.config(nx=int(rng.integers(20, 90)), nvx=nv, nvy=nv, length=float(rng.uniform(1e-4, 5e-4)),
+                     ey=-float(rng.uniform(2e6, 8e6)), delta_max=2.5, a_max_ev=400.0, j_src=1e5,
+                     physics_mask=mask, ex_external=1e5, t_e_ev=40.0, ln_lambda=10.0)
+        cfgs.append(c)
+        states.append(collisional_state(dict(c, physics_mask=c["physics_mask"] | W.BGK), 40 + m, 2e-3)
+                      .astype(np.float32))
+    steps = 20
+    with fk.Batch(cfgs) as b:
+        for v, f0 in zip(b.views, states):
+            v.write_state(f0, 2e-6, 0.0, 0)
+        b.step(steps)
+        b.sync()
+        for m, (c, v, f0) in enumerate(zip(cfgs, b.views, states)):
+            o = Oracle(c)
+            o.set_state(f0.astype(np.float64), 2e-6, 0)
+            o.step(steps)
+            if m != 1:
+                assert o.nu_dt_max() > 1e-3
+            st, orc = v.state(), o.record()
+            assert rel_l2(v.f(), o.f()) < 1e-5, m
+            compare_state(st, orc, 1e-5)
