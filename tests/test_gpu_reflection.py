@@ -116,3 +116,21 @@ def test_reflection_in_a_batch(fk):
             for q in ("g_pe", "g_see", "n_total"):
                 assert abs(st[q] - orc[q]) <= 1e-5 * abs(orc[q]) + 1e-30, (m, q)
             assert abs(st["sigma"] + st["sigma_lo"] - orc["sigma"]) <= 1e-5 * abs(orc["sigma"]), m
+
+
+def test_saturated_balance_with_reflection(fk):
+    """At saturation sigma stops changing, so by Eq 18 with reflection the
+    secondaries plus the reflected electrons balance the primaries:
+    Gamma_see / Gamma_pe = 1 - R_f (the paper's default run, R_f = 0.3)."""
+    cfg = dict(W.paper_default(), r_refl=0.3)
+    with fk.Solver(cfg, "f32", trace_cap=8192, trace_stride=100) as s:
+        done = False
+        for _ in range(80):
+            s.step(5000)
+            if s.saturated(50e-12, 1e-3):
+                done = True
+                break
+        st = s.state()
+    print("paper default with R_f = 0.3: sigma", st["sigma"] + st["sigma_lo"], "Gsee/Gpe", st["g_see"] / st["g_pe"])
+    assert done
+    assert abs(st["g_see"] / st["g_pe"] - 0.7) < 2e-3
