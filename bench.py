@@ -167,9 +167,10 @@ def main():
                     help="steps run before the warmup to drive the state into the avalanche")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (counter calibration)")
-    ap.add_argument("--workload", choices=("c1", "c4"), default="c1",
-                    help="c1: 2048x256x256 (the headline); c4: 4096x384x384 (no CPU baseline: one "
-                         "oracle step takes minutes there)")
+    ap.add_argument("--workload", choices=("c1", "c4", "c4slab"), default="c1",
+                    help="c1: 2048x256x256 (the headline); c4: 4096x384x384 (no CPU baseline); "
+                         "c4slab: one GPU's share of 4096x384x384 split over 8 GPUs in x "
+                         "(512x384x384 over 1/8 mm, the same cells)")
     ap.add_argument("--bgk", action="store_true",
                     help="with the electron-electron collision term (Eq 3-5, T_e 2 eV, ln Lambda 10), "
                          "starting from a thin Maxwellian background in every x plane so that every "
@@ -191,7 +192,13 @@ def main():
     from paper_2303_14119_amd import flashkin as fk
     from paper_2303_14119_amd import workloads as W
 
-    cfg = W.c1() if args.workload == "c1" else W.c4()
+    if args.workload == "c1":
+        cfg = W.c1()
+    elif args.workload == "c4":
+        cfg = W.c4()
+    else:
+        c4 = W.c4()
+        cfg = dict(c4, nx=c4["nx"] // 8, length=c4["length"] / 8)
     if args.bgk:
         cfg = dict(cfg, physics_mask=W.ALL | W.BGK, t_e_ev=2.0, ln_lambda=10.0)
     dev = torch.device("cuda:0")
@@ -269,7 +276,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": (f"plain single run, {cfg['nx']}x{cfg['nvx']}x{cfg['nvy']} cells over 1 mm, "
+        "config": {"workload": (("one GPU's x slab of the 4096x384x384 run split over 8 GPUs (wall and vacuum "
+                                 "boundaries stand in for the neighbours' half-planes), "
+                                 if args.workload == "c4slab" else "plain single run, ")
+                                + f"{cfg['nx']}x{cfg['nvx']}x{cfg['nvy']} cells over {cfg['length'] * 1e3:g} mm, "
                                 f"|E_y| {abs(cfg['ey']) / 1e6:g} MV/m, delta_max {cfg['delta_max']:g}, "
                                 f"A_max {cfg['a_max_ev']:g} eV, FP32 f, FP64 sigma and fluxes"
                                 + (", with e-e collisions (BGK, T_e 2 eV) from a 1e12 m^-3 background"
