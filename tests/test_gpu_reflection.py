@@ -134,3 +134,29 @@ def test_saturated_balance_with_reflection(fk):
     print("paper default with R_f = 0.3: sigma", st["sigma"] + st["sigma_lo"], "Gsee/Gpe", st["g_see"] / st["g_pe"])
     assert done
     assert abs(st["g_see"] / st["g_pe"] - 0.7) < 2e-3
+
+
+def test_c0_run_with_reflection_and_collisions_fp64(fk):
+    """The 128 x 64 x 64 parity run (1000 steps from f = 0) with both
+    optional parts of the step on: R_f = 0.3 and the collision term.  FP64
+    against the oracle along the whole trace."""
+    cfg = dict(W.c0(), physics_mask=W.ALL | W.BGK, t_e_ev=2.0, ln_lambda=10.0, r_refl=0.3)
+    o = Oracle(cfg)
+    otr = o.step(W.C0_STEPS, trace=True)
+    plain = Oracle(W.c0())
+    plain.step(W.C0_STEPS)
+    assert rel_l2(plain.f(), o.f()) > 1e-3          # the two parts change the run
+    with fk.Solver(cfg, "f64", trace_cap=2048) as s:
+        s.step(W.C0_STEPS)
+        s.sync()
+        gtr, lost = s.trace()
+        g, st = s.f(), s.state()
+    assert not lost and len(gtr) == W.C0_STEPS + 1
+    for a, b in zip(gtr[1::50], otr[::50]):
+        assert a["step"] == b["step"]
+        for q in ("g_pe", "g_see", "n_total"):
+            assert rel(a[q], b[q]) <= 1e-11 or abs(a[q] - b[q]) <= 1e-30, (a["step"], q)
+        assert rel(a["sigma"] + a["sigma_lo"], b["sigma"]) <= 1e-11 or abs(b["sigma"]) < 1e-30
+    assert rel_l2(g, o.f()) <= 1e-12
+    orc = o.record()
+    assert rel(st["sigma"] + st["sigma_lo"], orc["sigma"]) <= 1e-12
