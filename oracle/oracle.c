@@ -19,9 +19,16 @@
  *   - the SEE yield matrix (Eq 8-11), the primary and secondary wall fluxes
  *     (Eq 12-14), the half-Maxwellian emission boundary (Eq 15-16), the
  *     absorbing vacuum boundary (Eq 17) and the surface-charge update (Eq 18);
- *   - optionally a wall reflection coefficient R_f (Section 2, after Eq 14):
- *     a fraction R_f of the electrons reaching the wall is reflected
- *     specularly (v_x -> -v_x) into the emission row, the rest induces SEE;
+ *   - optionally a wall reflection coefficient R_f (Section 2, after Eq 14),
+ *     split into an elastic share (reflected specularly, v_x -> -v_x, into
+ *     the emission row) and an inelastic share (re-emitted with the Eq 15
+ *     shape at T_se); the rest of the arrivals induces SEE;
+ *   - optionally (ORC_NOSC) the field of the surface charge alone, without
+ *     the electrons' space charge: the setting of the single-particle
+ *     theory of Eq 19-20, used to separate the two in the tests;
+ *   - optionally (scheme 1) a second-order variant, not in the paper: each
+ *     sweep in flux form with minmod-limited slopes, and the split order
+ *     reversed on odd steps;
  *   - optionally (ORC_BGK) the electron-electron collision term: relaxation
  *     towards the Maxwellian of Eq 5 at T_e, at the frequency of Eq 4
  *     (Eq 3), evaluated on f^n and n^n and added after the source.
@@ -36,9 +43,12 @@
  *
  * Parity is pinned by the CPU tests (binomial closed forms of upwind
  * transport, uniform-acceleration shift, linear field for uniform charge,
- * particle conservation, SEY identities, emission normalisation; for the
- * collision term the textbook electron collision time, the geometric
- * relaxation of BGK alone and the temperature of its fixed point).
+ * particle conservation, SEY identities, emission normalisation, the
+ * table's energy/angle mapping and the VDF temperatures; for the collision
+ * term the textbook electron collision time, the geometric relaxation of
+ * BGK alone and the temperature of its fixed point; for the second-order
+ * variant Lax-Wendroff's exact transport of a quadratic, second-order
+ * convergence and the split-order centroid).
  */
 #include <math.h>
 #include <stdint.h>
@@ -63,6 +73,8 @@
 #define ORC_SEE  16u   /* secondary emission, Eq 12-16 */
 #define ORC_SELF 32u   /* E_x from sigma and the electron charge */
 #define ORC_BGK  64u   /* electron-electron collisions, Eq 3-5 */
+#define ORC_NOSC 128u  /* with ORC_SELF: E_x from sigma only, the electrons' space
+                          charge left out (the field of the Eq 19-20 theory) */
 
 typedef struct {
     int nx, nvx, nvy;
@@ -78,7 +90,10 @@ typedef struct {
     double ex_external;     /* uniform E_x added to the self field, V/m */
     double t_e_ev;          /* temperature of the collisional equilibrium (Eq 4-5), eV */
     double ln_lambda;       /* Coulomb logarithm of Eq 4 */
-    double r_refl;          /* wall reflection coefficient R_f (Section 2, after Eq 14), 0..1 */
+    double r_refl;          /* elastic (specular) share of the wall reflection R_f (Section 2, after Eq 14) */
+    double r_inel;          /* inelastic share of R_f: re-emitted with the Eq 15 shape at T_se */
+    int scheme;             /* 0: first-order upwind, Lie split x, v_x, v_y, source (Section 2);
+                               1: minmod-limited second order, split order reversed on odd steps */
 } orc_params;
 
 /* The observables of the state (f^n, sigma^n) after n steps. */
@@ -241,9 +256,11 @@ static orc_moments prologue(orc_sim* s)
     double below = 0.0;
     for (int k = 0; k < p->nx; ++k) {
         double enclosed = below + 0.5 * s->ne[k];
-        double self = (p->physics_mask & ORC_SELF)
-            ? s->sigma / (2.0 * ORC_EPS0) - ORC_E / ORC_EPS0 * s->dx * enclosed
-            : 0.0;
+        double self = 0.0;
+        if (p->physics_mask & ORC_SELF) {
+            self = s->sigma / (2.0 * ORC_EPS0);
+            if (!(p->physics_mask & ORC_NOSC)) self -= ORC_E / ORC_EPS0 * s->dx * enclosed;
+        }
         s->ex[k] = self + p->ex_external;
         below += s->ne[k];
     }
@@ -266,16 +283,20 @@ static orc_moments prologue(orc_sim* s)
         }
     }
 
-    /* only the fraction 1 - R_f of the arriving electrons induces SEE */
-    mo.g_see *= 1.0 - p->r_refl;
+    /* only the fraction 1 - R_f of the arriving electrons induces SEE; R_f
+       is split into an elastic (specular) and an inelastic share */
+    mo.g_see *= 1.0 - p->r_refl - p->r_inel;
 
-    /* Eq 15: emission boundary row at x = 0 for v_x > 0 */
+    /* Eq 15: emission boundary row at x = 0 for v_x > 0.  The inelastically
+       reflected electrons leave with the secondaries' shape (they have lost
+       their energy to the wall) */
+    double g_shape = mo.g_see + p->r_inel * mo.g_pe;
     double coef;
     if (p->emission_norm == 0)
-        coef = s->zsum > 0.0 ? mo.g_see / s->zsum : 0.0;
+        coef = s->zsum > 0.0 ? g_shape / s->zsum : 0.0;
     else {
         double mt = ORC_ME / (p->t_se_ev * ORC_E);
-        coef = mo.g_see / sqrt(2.0 * ORC_PI) * pow(mt, 1.5);
+        coef = g_shape / sqrt(2.0 * ORC_PI) * pow(mt, 1.5);
     }
     for (int i = 0; i < p->nvx; ++i)
         for (int j = 0; j < p->nvy; ++j) {
@@ -378,6 +399,119 @@ static double sweep_vy(orc_sim* s, const double* in, double* out)
                 out[idx(s, k, i, j)] = r;
             }
     return lost * s->dx * s->dvx * s->dvy;
+}
+
+/* ---- second-order sweeps (scheme 1) ------------------------------------
+   Each 1D advection at constant Courant number c (|c| <= 1) is taken in
+   flux form.  The value carried through a face is the upwind cell's value
+   moved towards the face by its limited slope: for c > 0 the face right of
+   cell m carries f_m + (1 - c)/2 s_m, for c < 0 the face left of cell m
+   carries f_m - (1 + c)/2 s_m, and f'_m = f_m - c (right face - left face).
+   s_m is the minmod of the two one-sided differences of cell m; it is zero
+   in the first and last cell of every line, so every boundary face (the
+   dielectric, the vacuum face, the velocity-box edges) carries the plain
+   upwind value and the wall, emission, escape and loss bookkeeping is the
+   same as in the first-order scheme.  With s = 0 everywhere the update is
+   the first-order upwind one. */
+static double minmod(double a, double b)
+{
+    if (a > 0.0 && b > 0.0) return a < b ? a : b;
+    if (a < 0.0 && b < 0.0) return a > b ? a : b;
+    return 0.0;
+}
+
+/* slope of cell m of a line of n cells, values v(m) = line[m * stride] */
+static double line_slope(const double* line, size_t stride, int m, int n)
+{
+    if (m <= 0 || m >= n - 1) return 0.0;
+    return minmod(line[m * stride] - line[(m - 1) * stride], line[(m + 1) * stride] - line[m * stride]);
+}
+
+/* the limited update of cell m; lo / hi are the values upwind of the first
+   and last face from outside the line (what flows in there) */
+static double line_update(const double* line, size_t stride, int m, int n, double c, double lo, double hi)
+{
+    double fm = line[m * stride];
+    double right, left;
+    if (c > 0.0) {
+        right = fm + 0.5 * (1.0 - c) * line_slope(line, stride, m, n);
+        left = m > 0 ? line[(m - 1) * stride] + 0.5 * (1.0 - c) * line_slope(line, stride, m - 1, n) : lo;
+    } else if (c < 0.0) {
+        left = fm - 0.5 * (1.0 + c) * line_slope(line, stride, m, n);
+        right = m < n - 1 ? line[(m + 1) * stride] - 0.5 * (1.0 + c) * line_slope(line, stride, m + 1, n) : hi;
+    } else {
+        return fm;
+    }
+    return fm - c * (right - left);
+}
+
+static void sweep_x2(orc_sim* s, const double* in, double* out)
+{
+    const orc_params* p = &s->p;
+    const size_t plane = (size_t)p->nvx * p->nvy;
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < p->nx; ++k)
+        for (int i = 0; i < p->nvx; ++i) {
+            double c = s->vx[i] * s->dt / s->dx;
+            for (int j = 0; j < p->nvy; ++j) {
+                const double* line = in + idx(s, 0, i, j);
+                double ghost = s->ghost[(size_t)i * p->nvy + j];
+                out[idx(s, k, i, j)] = line_update(line, plane, k, p->nx, c, ghost, 0.0);
+            }
+        }
+}
+
+static double sweep_vx2(orc_sim* s, const double* in, double* out)
+{
+    const orc_params* p = &s->p;
+    double lost = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : lost)
+    for (int k = 0; k < p->nx; ++k) {
+        double d = -ORC_E * s->ex[k] / ORC_ME * s->dt / s->dvx;
+        for (int i = 0; i < p->nvx; ++i)
+            for (int j = 0; j < p->nvy; ++j) {
+                const double* line = in + idx(s, k, 0, j);
+                out[idx(s, k, i, j)] = line_update(line, (size_t)p->nvy, i, p->nvx, d, 0.0, 0.0);
+                if (d > 0.0 && i == p->nvx - 1) lost += d * line[(size_t)i * p->nvy];
+                if (d < 0.0 && i == 0) lost += -d * line[0];
+            }
+    }
+    return lost * s->dx * s->dvx * s->dvy;
+}
+
+static double sweep_vy2(orc_sim* s, const double* in, double* out)
+{
+    const orc_params* p = &s->p;
+    double d = -ORC_E * p->ey / ORC_ME * s->dt / s->dvy;
+    double lost = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : lost)
+    for (int k = 0; k < p->nx; ++k)
+        for (int i = 0; i < p->nvx; ++i) {
+            const double* line = in + idx(s, k, i, 0);
+            for (int j = 0; j < p->nvy; ++j) {
+                out[idx(s, k, i, j)] = line_update(line, 1, j, p->nvy, d, 0.0, 0.0);
+                if (d > 0.0 && j == p->nvy - 1) lost += d * line[j];
+                if (d < 0.0 && j == 0) lost += -d * line[0];
+            }
+        }
+    return lost * s->dx * s->dvx * s->dvy;
+}
+
+/* Flux of the array entering an x sweep through the dielectric (v_x < 0,
+   absorbed) and through x = L (v_x > 0): the first and last cell's values,
+   as their slopes are zero. */
+static void boundary_outflow(const orc_sim* s, const double* f, double* wall, double* top)
+{
+    const orc_params* p = &s->p;
+    const double dv2 = s->dvx * s->dvy;
+    double w = 0.0, t = 0.0;
+    for (int i = 0; i < p->nvx; ++i)
+        for (int j = 0; j < p->nvy; ++j) {
+            if (s->vx[i] < 0.0) w += -s->vx[i] * f[idx(s, 0, i, j)] * dv2;
+            if (s->vx[i] > 0.0) t += s->vx[i] * f[idx(s, p->nx - 1, i, j)] * dv2;
+        }
+    *wall = w;
+    *top = t;
 }
 
 /* Eq 7 band source, added after the advections. */
@@ -524,17 +658,21 @@ static void fill_record(orc_sim* s, const orc_moments* mo, orc_record* r)
 }
 
 /* Advance n steps.  If trace is not NULL, trace[m] receives the observables
-   of the state after step m+1. */
+   of the state after step m+1.
+
+   Scheme 0 (the paper's): x, v_x, v_y, source in every step.  Scheme 1:
+   the limited sweeps in that order on even steps (step counter n even) and
+   in the reverse order (source, v_y, v_x, x) on odd steps, so that two
+   consecutive steps form a symmetric composition.  The wall fluxes, the
+   yield and the emission row come from f^n in both orders (the prologue);
+   on a reversed step the electrons absorbed at the wall and at x = L are
+   those of the array the x sweep transports (the wall cell after the
+   velocity sweeps), and Eq 18 charges the wall with that absorbed flux. */
 void orc_step(orc_sim* s, int64_t n, orc_record* trace)
 {
     const orc_params* p = &s->p;
     for (int64_t it = 0; it < n; ++it) {
         orc_moments mo = prologue(s);
-
-        /* Eq 18: the surface charge of the next step; reflected electrons
-           leave the wall again and deposit no charge */
-        double g_refl = (p->physics_mask & ORC_X) ? p->r_refl * mo.g_pe : 0.0;
-        double sigma_next = s->sigma + ORC_E * s->dt * (mo.g_see + g_refl - mo.g_pe);
 
         for (int k = 0; k < p->nx; ++k) {
             double d = fabs(-ORC_E * s->ex[k] / ORC_ME * s->dt / s->dvx);
@@ -546,10 +684,35 @@ void orc_step(orc_sim* s, int64_t n, orc_record* trace)
         double* a = s->f;
         double* b = s->g;
         double lost = 0.0, injected = 0.0;
-        if (p->physics_mask & ORC_X) { sweep_x(s, a, b); double* t = a; a = b; b = t; }
-        if (p->physics_mask & ORC_VX) { lost += sweep_vx(s, a, b); double* t = a; a = b; b = t; }
-        if (p->physics_mask & ORC_VY) { lost += sweep_vy(s, a, b); double* t = a; a = b; b = t; }
-        if (p->physics_mask & ORC_SRC) injected = add_source(s, a);
+        /* absorbed at the wall and escaped at x = L during the x sweep */
+        double g_abs = mo.g_pe, top_abs = mo.g_top;
+        const int second = p->scheme == 1;
+        const int reversed = second && (s->step & 1);
+        if (!reversed) {
+            if (p->physics_mask & ORC_X) {
+                if (second) sweep_x2(s, a, b); else sweep_x(s, a, b);
+                double* t = a; a = b; b = t;
+            }
+            if (p->physics_mask & ORC_VX) {
+                lost += second ? sweep_vx2(s, a, b) : sweep_vx(s, a, b);
+                double* t = a; a = b; b = t;
+            }
+            if (p->physics_mask & ORC_VY) {
+                lost += second ? sweep_vy2(s, a, b) : sweep_vy(s, a, b);
+                double* t = a; a = b; b = t;
+            }
+            if (p->physics_mask & ORC_SRC) injected = add_source(s, a);
+        } else {
+            if (p->physics_mask & ORC_SRC) injected = add_source(s, a);
+            if (p->physics_mask & ORC_VY) { lost += sweep_vy2(s, a, b); double* t = a; a = b; b = t; }
+            if (p->physics_mask & ORC_VX) { lost += sweep_vx2(s, a, b); double* t = a; a = b; b = t; }
+            if (p->physics_mask & ORC_X) {
+                boundary_outflow(s, a, &g_abs, &top_abs);
+                sweep_x2(s, a, b);
+                double* t = a; a = b; b = t;
+            }
+        }
+        if (!(p->physics_mask & ORC_X)) g_abs = top_abs = 0.0;
         if (p->physics_mask & ORC_BGK) {
             size_t cells = (size_t)p->nx * p->nvx * p->nvy;
             for (size_t c = 0; c < cells; ++c) a[c] += s->coll[c];
@@ -557,11 +720,15 @@ void orc_step(orc_sim* s, int64_t n, orc_record* trace)
         s->f = a;
         s->g = b;
 
-        s->sigma = sigma_next;
+        /* Eq 18: the surface charge of the next step.  Secondaries and the
+           reflected electrons (elastic R_f and inelastic shares, taken from
+           f^n like the yield) leave the wall; the absorbed electrons charge it */
+        double g_back = (p->physics_mask & ORC_X) ? (p->r_refl + p->r_inel) * mo.g_pe : 0.0;
+        s->sigma = s->sigma + ORC_E * s->dt * (mo.g_see + g_back - g_abs);
         s->step += 1;
 
         orc_moments nx = prologue(s);
-        double expected = s->dt * (mo.emitted - mo.g_pe - mo.g_top) + injected - lost;
+        double expected = s->dt * (mo.emitted - g_abs - top_abs) + injected - lost;
         s->last_loss_v = lost;
         s->last_resid = (nx.n_total - mo.n_total) - expected;
         if (trace) fill_record(s, &nx, &trace[it]);

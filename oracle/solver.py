@@ -17,6 +17,7 @@ EPS0 = 8.8541878128e-12
 X, VX, VY, SRC, SEE, SELF = 1, 2, 4, 8, 16, 32
 ALL = X | VX | VY | SRC | SEE | SELF
 BGK = 64   # electron-electron collisions (Eq 3-5); not part of ALL
+NOSC = 128  # with SELF: E_x from sigma alone, no electron space charge
 
 
 class _Params(C.Structure):
@@ -29,7 +30,7 @@ class _Params(C.Structure):
         ("x_src_hi", C.c_double), ("t_src_ev", C.c_double),
         ("emission_norm", C.c_int), ("physics_mask", C.c_uint),
         ("ex_external", C.c_double), ("t_e_ev", C.c_double), ("ln_lambda", C.c_double),
-        ("r_refl", C.c_double),
+        ("r_refl", C.c_double), ("r_inel", C.c_double), ("scheme", C.c_int),
     ]
 
 

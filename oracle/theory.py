@@ -33,6 +33,20 @@ def sigma_saturated(ey, delta_max, a_max_ev, a0_ev, ks=1.0):
     return 2.0 * EPS0 * abs(ey) * (0.5 * (a1 / a0_ev - 1.0)) ** -0.5
 
 
+def sigma_saturated_normal(ey, delta_max, a_max_ev, a0_ev, ks=1.0):
+    """Eq 19 for a secondary launched along the normal, without the cosine
+    average of Eq 20: the flight time 2 v0 / a_ex and the distance
+    a_ey t^2 / 2 must bring the energy from A0 to A1 with a_ex / a_ey =
+    E_x / E_y and E_x = sigma / 2 eps0.  Solved for sigma (C/m^2)."""
+    a1 = first_crossover_ev(delta_max, a_max_ev, ks)
+    if a1 is None or a1 <= a0_ev:
+        return None
+    # (2/m)(A1 - A0) = a_ey^2 t^2 with t = 2 v0 / a_ex and v0^2 = 2 A0 / m
+    # gives (a_ey / a_ex)^2 = (A1 - A0) / (4 A0)
+    ex = abs(ey) * math.sqrt(4.0 * a0_ev / (a1 - a0_ev))
+    return 2.0 * EPS0 * ex
+
+
 def flight_time(sigma, a0_ev):
     """Time of flight of a normally launched secondary, 2 v0 / |a_ex| with
     a_ex = e E_x / m and E_x = sigma / 2 eps0."""

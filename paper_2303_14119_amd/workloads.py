@@ -19,7 +19,10 @@ Parameter keys (SI units unless the name says eV):
   ex_external              uniform E_x added to the self field
   t_e_ev, ln_lambda        temperature and Coulomb logarithm of the electron-
                            electron collision term (Eq 3-5), used with BGK
-  r_refl                   wall reflection coefficient R_f (0: none)
+  r_refl                   elastic (specular) share of the wall reflection R_f (0: none)
+  r_inel                   inelastic share of R_f, re-emitted with the secondaries' shape
+  scheme                   0: first-order upwind (the paper's); 1: limited second order
+                           with the split order reversed on odd steps
 """
 import math
 
@@ -29,6 +32,7 @@ import numpy as np
 X, VX, VY, SRC, SEE, SELF = 1, 2, 4, 8, 16, 32
 ALL = X | VX | VY | SRC | SEE | SELF
 BGK = 64   # electron-electron collisions; opt-in, not part of ALL
+NOSC = 128  # with SELF: the field of the surface charge alone (no electron space charge)
 
 _E = 1.602176634e-19
 _ME = 9.1093837015e-31
@@ -44,6 +48,7 @@ VMAX_1KEV = speed_of(1000.0)
 _BASE = dict(
     dt=0.0, cfl=0.9, ks=1.0, t_se_ev=2.0, j_src=1.0e5, x_src_lo=10e-6, x_src_hi=15e-6,
     t_src_ev=2.0, emission_norm=0, physics_mask=ALL, ex_external=0.0, t_e_ev=2.0, ln_lambda=10.0, r_refl=0.0,
+    r_inel=0.0, scheme=0,
     vmax_x=VMAX_1KEV, vmax_y=VMAX_1KEV,
 )
 

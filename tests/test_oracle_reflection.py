@@ -77,3 +77,72 @@ def test_particle_balance_closes_with_reflection():
     tr = o.step(30, trace=True)
     for r in tr:
         assert abs(r["resid"]) <= 1e-13 * r["n_total"], r
+
+
+# ------------------------------------------------------------ inelastic share
+#
+# Reading of "elastic and inelastic reflection" (Section 2, after Eq 14):
+# R_f is split into an elastic share r_refl (specular, as above) and an
+# inelastic share r_inel; an inelastically reflected electron has given its
+# energy to the wall and leaves with the secondaries' half-Maxwellian of
+# Eq 15 at T_se.  1 - r_refl - r_inel of the arrivals induce SEE.
+
+def test_inelastic_share_leaves_with_the_emission_shape():
+    """Full inelastic reflection, nothing else at the wall: the emission row
+    is Gamma_pe times the Eq 15 shape normalised to unit flux, whatever the
+    arriving distribution; sigma cannot change (every electron leaves
+    again) and the particle balance closes."""
+    cfg = W.config(nx=12, nvx=16, nvy=8, length=1e-4, ey=-5e6, delta_max=2.5, a_max_ev=400.0,
+                   physics_mask=W.X | W.SEE, j_src=0.0, r_inel=1.0)
+    o = Oracle(cfg)
+    f0 = W.random_state((12, 16, 8), seed=6, scale=1e3)
+    o.set_state(f0, 2e-6, 0)
+    r = o.record()
+    t = o.tables()
+    assert r["g_see"] == 0.0 and r["g_pe"] > 0
+    want = r["g_pe"] * t["ghat"] / t["zsum"]
+    assert np.allclose(o.ghost(), want, rtol=1e-14, atol=0)
+    assert r["emitted"] == pytest.approx(r["g_pe"], rel=1e-13)
+    tr = o.step(20, trace=True)
+    assert all(x["sigma"] == pytest.approx(2e-6, rel=1e-15) for x in tr)
+    assert max(abs(x["resid"]) / x["n_total"] for x in tr) < 1e-13
+
+
+def test_shares_split_the_arrivals():
+    """Elastic 0.2 and inelastic 0.3: Gamma_see scales by 0.5, the row
+    carries Gamma_see + 0.3 Gamma_pe in the emission shape plus the mirrored
+    wall cell times 0.2, and Eq 18 keeps (Gamma_see + 0.5 Gamma_pe -
+    Gamma_pe) dt e."""
+    cfg = W.config(nx=12, nvx=16, nvy=8, length=1e-4, ey=-5e6, delta_max=2.5, a_max_ev=400.0,
+                   physics_mask=W.X | W.SEE, j_src=0.0)
+    f0 = W.random_state((12, 16, 8), seed=3, scale=1e3)
+    o0 = Oracle(cfg)
+    o0.set_state(f0, 1e-6, 0)
+    r0 = o0.record()
+    o = Oracle(dict(cfg, r_refl=0.2, r_inel=0.3))
+    o.set_state(f0, 1e-6, 0)
+    r = o.record()
+    t = o.tables()
+    assert r["g_see"] == pytest.approx(0.5 * r0["g_see"], rel=1e-14)
+    mirror = np.zeros((16, 8))
+    mirror[8:] = 0.2 * f0[0, ::-1][8:]
+    want = (r["g_see"] + 0.3 * r["g_pe"]) * t["ghat"] / t["zsum"] + mirror
+    assert np.allclose(o.ghost(), want, rtol=1e-13, atol=0)
+    assert r["emitted"] == pytest.approx(r["g_see"] + 0.5 * r["g_pe"], rel=1e-12)
+    tr = o.step(1, trace=True)
+    e = 1.602176634e-19
+    assert tr[0]["sigma"] == pytest.approx(1e-6 + e * o.dt * (r["g_see"] + 0.5 * r["g_pe"] - r["g_pe"]), rel=1e-13)
+
+
+def test_saturated_balance_with_inelastic_share():
+    """At saturation Eq 18 balances Gamma_see + r_inel Gamma_pe = Gamma_pe:
+    the mean yield settles at 1 - r_inel (reduced grid of the paper's
+    default run, 20 um, 64 x 65 x 33)."""
+    cfg = dict(W.paper_default(), nx=64, nvx=65, nvy=33, dt=0.0, cfl=0.9, r_inel=0.3)
+    o = Oracle(cfg)
+    tr = o.step(int(round(1.0e-9 / o.dt)), trace=True)
+    tail = tr[-200:]
+    for r in tail:
+        assert abs(r["g_see"] / r["g_pe"] - 0.7) < 2e-3
+    assert tail[-1]["sigma"] > 0
+    assert max(abs(r["resid"]) / r["n_total"] for r in tr if r["n_total"] > 0) < 1e-12
