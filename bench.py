@@ -1,10 +1,12 @@
 #!/usr/bin/env python3
 """Throughput of the 1D2V flashover step on one MI355X.
 
-Workload: 2048 (x) x 256 (v_x) x 256 (v_y) cells = 134,217,728 (1 mm, |E_y| =
-8 MV/m, delta_max = 2.2, A_max = 350 eV), FP32 f with FP64 sigma and fluxes.
-The state is first driven into the avalanche so the timed steps move real
-data; inputs are resident in HBM before the timed region starts.
+Workload (default): 4096 (x) x 384 (v_x) x 384 (v_y) cells = 603,979,776
+(1 mm, |E_y| = 6 MV/m, delta_max = 2.8, A_max = 450 eV), FP32 f with FP64
+sigma and fluxes: the largest single-GPU run (2.4 GB per f buffer).
+``--workload c1`` runs 2048 x 256 x 256 (8 MV/m, delta_max 2.2, A_max
+350 eV).  The state is first driven into the avalanche so the timed steps
+move real data; inputs are resident in HBM before the timed region starts.
 
 One step = the fused sweep kernel over all of f plus the reduction/field
 kernel (every part of the method).  ``value`` is cell-updates per second of
@@ -12,7 +14,7 @@ the timed steps.  The roofline object prices the sweep kernel at its
 algorithmic traffic (read f once, write f once: 8 bytes per cell in FP32)
 against the MI355X HBM peak, with the kernel's launch durations measured by
 HIP events on the library's stream.  The CPU baseline is the FP64 oracle on a
-bounded sample of the same workload.
+bounded sample of the same workload (built for the host it runs on).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 """
@@ -28,7 +30,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "sweep_c1_rocprof.md")
+PROFILE_SUMMARY = {"c1": os.path.join(ROOT, "profiles", "sweep_c1_rocprof.md"),
+                   "c4": os.path.join(ROOT, "profiles", "sweep_c4_rocprof.md")}
 
 
 def kernel_source_digest():
@@ -45,12 +48,13 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(workload):
     """HBM bytes per sweep launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source."""
-    if not os.path.exists(PROFILE_SUMMARY):
+    summary of the workload, if it was taken on the current kernel source."""
+    path = PROFILE_SUMMARY.get(workload)
+    if not path or not os.path.exists(path):
         return None
-    text = open(PROFILE_SUMMARY).read()
+    text = open(path).read()
     m_src = re.search(r"kernel_source_digest:\s*([0-9a-f]+)", text)
     m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
     if not m_src or not m_b or m_src.group(1) != kernel_source_digest():
@@ -58,26 +62,38 @@ def measured_traffic():
     return float(m_b.group(1))
 
 
-def cpu_baseline(cfg, budget_s=12.0):
-    """FP64 oracle on the host: whole steps of the same workload until about
-    budget_s seconds of CPU work have run."""
-    from oracle.solver import Oracle, get_threads, set_threads
+def cpu_baseline(cfg, budget_s=12.0, budget_1t_s=6.0):
+    """FP64 oracle on the host, built there with -O3 -march=native: whole
+    steps of the same workload until about budget_s seconds of CPU work have
+    run on all the host's threads (at most 16, the box's share), then about
+    budget_1t_s seconds on one thread."""
+    from oracle import solver
+    solver.use_native_build()
     threads = min(16, os.cpu_count() or 1)
-    set_threads(threads)
-    o = Oracle(cfg)
-    o.step(1)                       # first touch of the arrays
     cells = cfg["nx"] * cfg["nvx"] * cfg["nvy"]
-    n, t0 = 0, time.perf_counter()
-    while True:
-        o.step(1)
-        n += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s:
-            break
+    o = solver.Oracle(cfg)
+
+    def timed(nthreads, budget):
+        solver.set_threads(nthreads)
+        o.step(1)                   # first touch of the arrays / warm caches
+        n, t0 = 0, time.perf_counter()
+        while True:
+            o.step(1)
+            n += 1
+            el = time.perf_counter() - t0
+            if el >= budget:
+                return n, el, solver.get_threads()
+
+    n, el, used = timed(threads, budget_s)
+    n1, el1, _ = timed(1, budget_1t_s)
     o.close()
-    return {"value": cells * n / el / 1e9, "unit": "Gcell-updates/s", "cores": get_threads(),
+    shape = f"{cfg['nx']}x{cfg['nvx']}x{cfg['nvy']}"
+    return {"value": cells * n / el / 1e9, "unit": "Gcell-updates/s", "cores": used,
             "kind": "oracle",
-            "sample": f"{n} whole FP64 steps of the same 2048x256x256 workload ({el:.1f} s)"}
+            "sample": f"{n} whole FP64 steps of the same {shape} workload on {used} threads ({el:.1f} s); "
+                      f"oracle built with gcc -O3 -march=native on this host",
+            "value_1_thread": cells * n1 / el1 / 1e9,
+            "sample_1_thread": f"{n1} whole steps on 1 thread ({el1:.1f} s)"}
 
 
 def bench_batch(args):
@@ -161,14 +177,15 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--batch-default", action="store_true",
                     help="batch mode: the default tiling and launch mode instead of the autotuned choice")
-    ap.add_argument("--sample-every", type=int, default=16,
-                    help="HIP events around every n-th step's kernels in the timed region")
+    ap.add_argument("--sample-every", type=int, default=0,
+                    help="HIP events around every n-th step's kernels in the timed region "
+                         "(0: every step when --steps is below 100, else every 16th)")
     ap.add_argument("--pre-steps", type=int, default=3000,
                     help="steps run before the warmup to drive the state into the avalanche")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (counter calibration)")
-    ap.add_argument("--workload", choices=("c1", "c4", "c4slab"), default="c1",
-                    help="c1: 2048x256x256 (the headline); c4: 4096x384x384 (no CPU baseline); "
+    ap.add_argument("--workload", choices=("c1", "c4", "c4slab"), default="c4",
+                    help="c4: 4096x384x384 (the headline, the largest single-GPU run); c1: 2048x256x256; "
                          "c4slab: one GPU's share of 4096x384x384 split over 8 GPUs in x "
                          "(512x384x384 over 1/8 mm, the same cells)")
     ap.add_argument("--bgk", action="store_true",
@@ -179,6 +196,8 @@ def main():
                     help="c1: the headline line (default); batch: the 64-instance batched sweep; "
                          "mlp: surrogate training steps (both for profiling, one JSON line each)")
     args = ap.parse_args()
+    if args.sample_every <= 0:
+        args.sample_every = 1 if args.steps < 100 else 16
     if args.gpus != 1:
         print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); a run over several GPUs "
               "would split x into slabs exchanging one half-plane per neighbour and step", file=sys.stderr)
@@ -262,7 +281,7 @@ def main():
     field_ms = kt["field_ms"] / max(kt["field_n"], 1)
     bytes_per_launch = 8.0 * cells
     achieved = bytes_per_launch / (sweep_ms * 1e-3) / 1e9
-    traffic = measured_traffic() if args.workload == "c1" and not args.bgk else None   # counters taken on c1
+    traffic = measured_traffic(args.workload) if not args.bgk else None
     out = {
         "metric": "Gcell-updates/s",
         "value": round(value, 3),
@@ -297,7 +316,7 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_per_launch},
         "cpu_baseline": None,
     }
-    if not args.no_cpu and args.workload == "c1" and not args.bgk:
+    if not args.no_cpu and args.workload in ("c1", "c4") and not args.bgk:
         out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out), flush=True)
 

@@ -37,7 +37,8 @@
 extern "C" {
 #endif
 
-#define FK_ABI_VERSION 4u   /* 2: fk_batch_info_t gained single_threads; 3: fk_params gained t_e_ev, ln_lambda; 4: r_refl */
+#define FK_ABI_VERSION 5u   /* 2: fk_batch_info_t gained single_threads; 3: fk_params gained t_e_ev, ln_lambda; 4: r_refl;
+                              5: r_inel, scheme */
 
 /* element type of f */
 enum { FK_F32 = 0, FK_F64 = 1 };
@@ -63,7 +64,28 @@ enum {
      * Taken explicitly on f^n and n^n and added to the swept f; the
      * Maxwellian is normalised on the grid, so the term moves no electrons
      * between x planes. */
-    FK_PHYS_BGK = 64
+    FK_PHYS_BGK = 64,
+    /* With FK_PHYS_SELF_FIELD: E_x = sigma / 2 eps0 (+ ex_external) at every
+     * x, the electrons' own space charge left out.  This is the field of the
+     * single-particle theory of Eq 19-20 (Section 3); it separates the space
+     * charge's share of the saturated sigma.  Opt-in. */
+    FK_PHYS_NO_SPACE_CHARGE = 128
+};
+
+/* advection scheme (fk_params.scheme) */
+enum {
+    FK_SCHEME_UPWIND = 0,   /* the paper's explicit first-order upwind step (Section 2, after Eq 2), split
+                             * x, v_x, v_y, source */
+    FK_SCHEME_LIMITED2 = 1  /* an accuracy extension beyond the paper for coarse grids: each 1D sweep in flux
+                             * form with a minmod-limited slope (the face carries the upwind cell's value
+                             * moved towards the face by (1 - |c|)/2 times its slope; slopes are zero in
+                             * the first and last cell of every line, so every boundary face carries the
+                             * upwind value as in scheme 0), and the split order reversed on odd steps
+                             * (source, v_y, v_x, x) so that two steps form a symmetric composition.  On
+                             * a reversed step the electrons absorbed at the wall and at x = L are those
+                             * of the array the x sweep transports; the yield, emission row and
+                             * reflection still come from f^n.  FK_F32 or FK_F64; not with FK_PHYS_BGK or
+                             * in a batch (FK_E_INVALID) */
 };
 
 /* error codes */
@@ -106,10 +128,17 @@ typedef struct {
     int32_t tile_planes;     /* x planes per tile; 0: chosen at creation from the sweep kernel's occupancy: the longest run (16..128) that keeps 8 waves resident per compute unit, or all a unit holds, with the workgroups spread evenly (fk_validate reports a host-side estimate, fk_query the choice); batch instances get 16 */
     double t_e_ev;           /* FK_PHYS_BGK: temperature of the collisional equilibrium (Eq 4-5), eV, > 0 */
     double ln_lambda;        /* FK_PHYS_BGK: Coulomb logarithm of Eq 4 (the paper: 10), > 0 */
-    double r_refl;           /* wall reflection coefficient R_f in [0, 1] (Section 2, after Eq 14): a fraction
-                              * R_f of the electrons reaching the dielectric returns specularly (v_x -> -v_x)
-                              * through the emission row, 1 - R_f induces SEE (Gamma_see scales by 1 - R_f),
-                              * and reflected electrons deposit no charge in Eq 18.  0: no reflection */
+    double r_refl;           /* elastic share of the wall reflection coefficient R_f (Section 2, after
+                              * Eq 14), in [0, 1]: a fraction r_refl of the electrons reaching the dielectric
+                              * returns specularly (v_x -> -v_x) through the emission row.  0: none */
+    double r_inel;           /* inelastic share of R_f, in [0, 1 - r_refl]: a fraction r_inel of the arrivals
+                              * has given its energy to the wall and leaves with the secondaries' Eq 15
+                              * half-Maxwellian at t_se_ev (the emission row carries Gamma_see + r_inel
+                              * Gamma_pe in that shape).  1 - r_refl - r_inel of the arrivals induce SEE
+                              * (Gamma_see scales by it), and reflected electrons of either share deposit no
+                              * charge in Eq 18.  0: none */
+    int32_t scheme;          /* FK_SCHEME_UPWIND or FK_SCHEME_LIMITED2 */
+    int32_t reserved0;       /* 0 */
 } fk_params;
 
 /* Observables of the state (f^n, sigma^n) after n steps.  The fluxes are
@@ -120,9 +149,9 @@ typedef struct {
     double sigma;            /* surface charge sigma^n, C/m^2 (Eq 18) */
     double sigma_lo;         /* compensation term of the sigma sum (sigma + sigma_lo is the value) */
     double g_pe;             /* primary flux into the wall, 1/(m^2 s) (Eq 13-14) */
-    double g_see;            /* secondary flux (Eq 12, 14), times 1 - r_refl */
+    double g_see;            /* secondary flux (Eq 12, 14), times 1 - r_refl - r_inel */
     double g_top;            /* flux leaving through x = L */
-    double emitted;          /* flux carried by the emission row, sum v_x f_ghost dv_x dv_y (secondaries plus reflected) */
+    double emitted;          /* flux carried by the emission row, sum v_x f_ghost dv_x dv_y (secondaries plus both reflected shares) */
     double loss_v;           /* electrons/m^2 lost through the velocity-box edges in step n */
     double n_total;          /* electrons/m^2 in the domain */
     double resid;            /* particle balance residual of step n, electrons/m^2 */

@@ -47,12 +47,23 @@ class Record(C.Structure):
 
 
 _lib = None
+_native = False
+
+
+def use_native_build():
+    """Load the host-tuned build (-march=native, compiled on this machine)
+    instead of the portable one; only before the first oracle call (the
+    benchmark's CPU baseline)."""
+    global _native
+    if _lib is not None:
+        raise RuntimeError("the oracle library is already loaded")
+    _native = True
 
 
 def lib():
     global _lib
     if _lib is None:
-        path = _build.build(force=False)
+        path = _build.build(force=_native, native=_native)
         L = C.CDLL(path)
         P = C.POINTER
         L.orc_create.restype = C.c_void_p

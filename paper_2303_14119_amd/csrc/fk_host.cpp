@@ -1,6 +1,7 @@
 // fk_host.cpp -- host-only parts of the C-ABI: parameter validation, the
 // derived layout, error strings and the saturation test.  Nothing here
 // touches the GPU, so these calls work on machines without one.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -9,13 +10,24 @@
 namespace fk {
 
 static thread_local std::string g_create_error;
+static thread_local const char* g_static_error = nullptr;   // set by calls that must not allocate
 
-const char* global_error() { return g_create_error.c_str(); }
+const char* global_error() { return g_static_error ? g_static_error : g_create_error.c_str(); }
 
 int set_error(std::string* slot, int code, const std::string& msg)
 {
-    if (slot) *slot = msg;
-    else g_create_error = msg;
+    if (slot) {
+        *slot = msg;
+    } else {
+        g_static_error = nullptr;
+        g_create_error = msg;
+    }
+    return code;
+}
+
+int set_static_error(int code, const char* msg)
+{
+    g_static_error = msg;
     return code;
 }
 
@@ -28,6 +40,13 @@ size_t sweep_lds(int ti, int block, int kc, int elem, bool bgk)
     const int waves = (block + 63) / 64;
     const size_t tab = bgk ? (size_t)4 * kc + ti : (size_t)2 * kc;
     return (size_t)2 * ti * (block + 2) * elem + (size_t)kc * waves * 8 + (size_t)waves * 4 * 8 + (size_t)waves * tab * elem;
+}
+
+size_t sweep2_lds(int ti, int block, int kc, int elem)
+{
+    const int waves = (block + 63) / 64;
+    return (size_t)2 * (ti + 4) * (block + 4) * elem + (size_t)kc * waves * 8 + (size_t)waves * 6 * 8 +
+           (size_t)waves * 2 * (kc + 4) * elem;
 }
 
 int derive_layout(const fk_params* p, Layout* L, std::string* why)
@@ -48,11 +67,15 @@ int derive_layout(const fk_params* p, Layout* L, std::string* why)
     if (!(p->j_src >= 0) || !std::isfinite(p->j_src)) return bad("j_src must be >= 0");
     if (!(p->x_src_hi >= p->x_src_lo)) return bad("x_src_hi must be >= x_src_lo");
     if (p->emission_norm != FK_EMIT_DISCRETE && p->emission_norm != FK_EMIT_ANALYTIC) return bad("bad emission_norm");
-    if (p->physics_mask & ~(uint32_t)(FK_PHYS_ALL | FK_PHYS_BGK)) return bad("unknown physics_mask bits");
+    if (p->physics_mask & ~(uint32_t)(FK_PHYS_ALL | FK_PHYS_BGK | FK_PHYS_NO_SPACE_CHARGE)) return bad("unknown physics_mask bits");
     const bool bgk = (p->physics_mask & FK_PHYS_BGK) != 0;
     if (bgk && !(p->t_e_ev > 0 && std::isfinite(p->t_e_ev))) return bad("t_e_ev must be > 0 and finite with FK_PHYS_BGK");
     if (bgk && !(p->ln_lambda > 0 && std::isfinite(p->ln_lambda))) return bad("ln_lambda must be > 0 and finite with FK_PHYS_BGK");
     if (!(p->r_refl >= 0 && p->r_refl <= 1)) return bad("r_refl must be in [0, 1]");
+    if (!(p->r_inel >= 0 && p->r_inel <= 1 - p->r_refl)) return bad("r_inel must be in [0, 1 - r_refl]");
+    if (p->scheme != FK_SCHEME_UPWIND && p->scheme != FK_SCHEME_LIMITED2) return bad("scheme must be FK_SCHEME_UPWIND or FK_SCHEME_LIMITED2");
+    if (p->scheme == FK_SCHEME_LIMITED2 && bgk) return bad("FK_SCHEME_LIMITED2 does not take FK_PHYS_BGK");
+    if (p->reserved0 != 0) return bad("reserved0 must be 0");
     if (p->trace_stride < 1 || p->trace_cap < 1) return bad("trace_stride and trace_cap must be >= 1");
     if (p->tile_rows != 0 && p->tile_rows != 4 && p->tile_rows != 8 && p->tile_rows != 12 && p->tile_rows != 16)
         return bad("tile_rows must be 0, 4, 8, 12 or 16");
@@ -92,6 +115,48 @@ int derive_layout(const fk_params* p, Layout* L, std::string* why)
 
     // launch shape: one thread per v_y column; tiles of ti v_x rows and kc x planes
     l.block = ((p->nvy + 63) / 64) * 64;
+    l.scheme = p->scheme;
+    if (p->scheme == FK_SCHEME_LIMITED2) {
+        // second order: 8 rows (FP32) or 4 (FP64) where the v_y exchange of
+        // ti + 4 rows fits; a single launch over every tile
+        int ti = p->tile_rows;
+        if (ti == 0) {
+            ti = l.elem == 4 ? 8 : 4;
+            while (ti > 4 && sweep2_lds(ti, l.block, 4, l.elem) > kLdsBudget) ti /= 2;
+        }
+        if (ti != 4 && ti != 8) return bad("FK_SCHEME_LIMITED2 takes tile_rows 4 or 8");
+        if (sweep2_lds(ti, l.block, 4, l.elem) > kLdsBudget)
+            return bad("FK_SCHEME_LIMITED2: the v_y exchange does not fit in LDS (nvy up to 960 in FP32 with 4-row tiles, "
+                       "512 with 8; 448 in FP64)");
+        l.ti = ti;
+        l.n_it = (p->nvx + ti - 1) / ti;
+        int kc = p->tile_planes;
+        if (kc == 0) {
+            const int target = 1024;
+            int nkc = (target + l.n_it - 1) / l.n_it;
+            kc = (p->nx + nkc - 1) / nkc;
+            kc = std::max(16, std::min(kc, 128));
+            while (kc > 4 && sweep2_lds(ti, l.block, kc, l.elem) > kLdsBudget) kc = kc > 16 ? kc - 16 : kc / 2;
+        }
+        if (kc > p->nx) kc = p->nx;
+        l.kc = kc;
+        l.n_kc = (p->nx + kc - 1) / kc;
+        l.nwg = l.n_it * l.n_kc;
+        l.n_fast = l.n_it;
+        l.n_generic = 0;
+        l.lds_sweep = sweep2_lds(ti, l.block, kc, l.elem);
+        l.lds_moments = (size_t)kc * (l.block / 64) * 8 + (size_t)(l.block / 64) * 4 * 8;
+        if (l.lds_sweep > kLdsBudget) return bad("tile needs more LDS than a workgroup has; lower tile_planes");
+        l.n_it_cap = (p->nvx + 3) / 4;
+        l.nwg_cap = l.n_it_cap * ((p->nx + 3) / 4);
+        const uint64_t v2 = (uint64_t)p->nvx * p->nvy;
+        l.bytes_device = 2ull * cells * l.elem + v2 * (8 * 3 + l.elem) + (uint64_t)p->nx * 8 * 9 +
+                         (uint64_t)(p->nvx + p->nvy) * l.elem +
+                         (uint64_t)p->nx * l.n_it_cap * 8 + (uint64_t)l.n_it_cap * 44 + (uint64_t)l.nwg_cap * 8 +
+                         sizeof(DevState) + (uint64_t)p->trace_cap * sizeof(fk_state) + 4096;
+        *L = l;
+        return FK_OK;
+    }
     int ti = p->tile_rows;
     if (ti == 0) {
         // FP32: 8 rows keep the fast body at four waves per SIMD, best up to
@@ -123,7 +188,9 @@ int derive_layout(const fk_params* p, Layout* L, std::string* why)
         kc = (p->nx + nkc - 1) / nkc;
         if (kc < 16) kc = 16;
         if (kc > 128) kc = 128;
-        while (kc > 16 && sweep_lds(ti, l.block, kc, l.elem, bgk) > kLdsBudget) kc -= 16;
+        // wide FP64 blocks leave little LDS for the per-plane tables: shorter
+        // x runs, down to 4 planes
+        while (kc > 4 && sweep_lds(ti, l.block, kc, l.elem, bgk) > kLdsBudget) kc = kc > 16 ? kc - 16 : kc / 2;
     }
     if (kc > p->nx) kc = p->nx;
     l.kc = kc;
@@ -143,7 +210,7 @@ int derive_layout(const fk_params* p, Layout* L, std::string* why)
     const uint64_t v2 = (uint64_t)p->nvx * p->nvy;
     l.bytes_device = 2ull * cells * l.elem + v2 * (8 * 3 + l.elem) + (uint64_t)p->nx * 8 * 9 +
                      (uint64_t)(p->nvx + p->nvy) * l.elem +
-                     (uint64_t)p->nx * l.n_it_cap * 8 + (uint64_t)l.n_it_cap * 28 + (uint64_t)l.nwg_cap * 8 +
+                     (uint64_t)p->nx * l.n_it_cap * 8 + (uint64_t)l.n_it_cap * 44 + (uint64_t)l.nwg_cap * 8 +
                      sizeof(DevState) + (uint64_t)p->trace_cap * sizeof(fk_state) + 4096;
     *L = l;
     return FK_OK;

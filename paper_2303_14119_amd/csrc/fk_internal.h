@@ -45,6 +45,7 @@ struct Layout {
     int64_t cells;
     int elem;                    // bytes per f element
     int bgk;                     // 1: the collision term (FK_PHYS_BGK) is on
+    int scheme;                  // FK_SCHEME_UPWIND or FK_SCHEME_LIMITED2
     int block;                   // threads of the sweep workgroup (one per v_y column)
     int ti;                      // v_x rows per tile
     int kc;                      // x planes per tile
@@ -57,6 +58,11 @@ struct Layout {
 
 int derive_layout(const fk_params* p, Layout* L, std::string* why);
 size_t sweep_lds(int ti, int block, int kc, int elem, bool bgk);
+// LDS of a second-order sweep workgroup: the v_y exchange of TI + 4 rows with
+// two halo columns each side (double-buffered), the plane sums, the
+// reduction slots and each wave's per-plane coefficients for the chunk and
+// two planes on each side
+size_t sweep2_lds(int ti, int block, int kc, int elem);
 
 // Number of rows among r = 0..ti+1 of v_x tile `it` (rows i = it*ti - 1 + r)
 // with v_x <= 0, i.e. 2 i + 1 <= nvx: the split point of the fast sweep body.
@@ -86,6 +92,9 @@ __host__ __device__ inline bool tile_is_special(int it, int ti, int nvx)
     return (it + 1) * ti <= nvx || tile_split(it, ti, nvx) == 0;
 }
 int set_error(std::string* slot, int code, const std::string& msg);
+// error of the calling thread's last failed call that has no object, from a
+// message with static storage (no allocation)
+int set_static_error(int code, const char* msg);
 const char* global_error();
 
 // Block of device buffers of one instance (owned by a context or a batch).
@@ -101,6 +110,7 @@ struct Buffers {
     double* part_wall;// [n_it][2]
     double* part_top; // [n_it]
     double* part_lv;  // [nwg]
+    double* part_abs; // [n_it][2]: absorbed at the wall and at x = L (reversed second-order steps)
     double* plane_sum;// [nx]   plane sums reduced over the v_x tiles (single contexts)
     double* ne;       // [nx]
     double* ex;       // [nx]

@@ -133,6 +133,7 @@ struct SweepArgs {
     double* __restrict__ part_wall;     // [n_it][2]
     double* __restrict__ part_top;      // [n_it]
     double* __restrict__ part_lv;       // [nwg]
+    double* __restrict__ part_abs;      // [n_it][2] absorbed at the wall / x = L (reversed second-order steps)
     int nx, nvx, nvy, n_it, kc;
     double dvx, dt_dx;                  // v_x of row i is cell_v(i, nvx, dvx)
     double dy;                          // signed v_y Courant number
@@ -541,6 +542,8 @@ struct FieldArgs {
     const double* __restrict__ part_wall;   // [n_it][2]  wall primary, wall secondary
     const double* __restrict__ part_top;    // [n_it]     flux through x = L
     const double* __restrict__ part_lv;     // [nwg]      velocity-box outflow
+    const double* __restrict__ part_abs;    // [n_it][2]  absorbed at the wall and at x = L by a reversed
+                                            //            second-order step (read when abs_from_sweep)
     const double* __restrict__ consts;  // zsum, srcnorm, injected per step, Eq 15 prefactor
     double* __restrict__ ne;
     double* __restrict__ ex;
@@ -554,7 +557,10 @@ struct FieldArgs {
     int emission_norm, trace_stride, trace_cap;
     double dx, dv2, dt, dvx, ex_ext;
     double nudt_per_n;              // dt nu_ee / n_e of Eq 4 (0: no collision term)
-    double r_refl;                  // wall reflection coefficient R_f
+    double r_refl;                  // elastic (specular) share of the wall reflection R_f
+    double r_inel;                  // inelastic share of R_f, re-emitted in the Eq 15 shape
+    int abs_from_sweep;             // 1: the step's x sweep transported f after the velocity sweeps
+                                    //    (reversed second-order step); its absorbed fluxes are in part_abs
 };
 
 // Reduction of the moment partials of the new f over the v_x tiles (fixed
@@ -637,11 +643,15 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
     }
     // wall, top and velocity-box partials: strided per thread, then over the
     // waves in order
-    double pe = 0.0, see = 0.0, top = 0.0, lv = 0.0;
+    double pe = 0.0, see = 0.0, top = 0.0, lv = 0.0, abw = 0.0, abt = 0.0;
     for (int u = t; u < a.n_it; u += T) {
         pe += a.part_wall[2 * u];
         see += a.part_wall[2 * u + 1];
         top += a.part_top[u];
+        if (a.abs_from_sweep) {
+            abw += a.part_abs[2 * u];
+            abt += a.part_abs[2 * u + 1];
+        }
     }
     if (a.advance)
         for (int w = t; w < a.nwg; w += T) lv += a.part_lv[w];
@@ -653,16 +663,23 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
     if (lane == 0) excl = 0.0;
     double* wtot = sh;              // [nw]
     double* red = sh + 64;          // [nw][6]
+    double* red2 = red + 6 * 16;    // [nw][2]
     if (lane == 63) wtot[wave] = incl;
     pe = wave_sum(pe);
     see = wave_sum(see);
     top = wave_sum(top);
     lv = wave_sum(lv);
+    if (a.abs_from_sweep) {
+        abw = wave_sum(abw);
+        abt = wave_sum(abt);
+    }
     if (lane == 0) {
         red[wave * 6 + 0] = pe;
         red[wave * 6 + 1] = see;
         red[wave * 6 + 2] = top;
         red[wave * 6 + 3] = lv;
+        red2[wave * 2 + 0] = abw;
+        red2[wave * 2 + 1] = abt;
     }
     __syncthreads();
     double wave_below = 0.0, total = 0.0;
@@ -672,11 +689,24 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
     }
     const double below0 = wave_below + excl;
 
+    // electrons the step's x sweep absorbed at the wall and let out at x = L:
+    // the fluxes of f^n, or on a reversed second-order step those of the
+    // array after the velocity sweeps (summed over the waves in order)
+    double g_abs = old.g_pe, top_abs = old.g_top;
+    if (a.abs_from_sweep && (a.mask & FK_PHYS_X)) {
+        double w0 = 0.0, w1 = 0.0;
+        for (int w = 0; w < nw; ++w) {
+            w0 += red2[w * 2 + 0];
+            w1 += red2[w * 2 + 1];
+        }
+        g_abs = w0 * a.dv2;
+        top_abs = w1 * a.dv2;
+    }
     double sig = old.sigma, sig_lo = old.sigma_lo;
     if (a.advance) {
-        // Eq 18 with the fluxes of f^n, Neumaier-compensated across steps
-        // reflected electrons (r_refl g_pe) leave the wall again
-        const double inc = kE * a.dt * (old.g_see + a.r_refl * old.g_pe - old.g_pe);
+        // Eq 18 with the fluxes of f^n, Neumaier-compensated across steps;
+        // reflected electrons of both shares leave the wall again
+        const double inc = kE * a.dt * (old.g_see + (a.r_refl + a.r_inel) * old.g_pe - g_abs);
         const double s = sig + inc;
         if (fabs(sig) >= fabs(inc)) sig_lo += (sig - s) + inc;
         else sig_lo += (inc - s) + sig;
@@ -689,7 +719,9 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
     const double e_wall = sigma_now / (2.0 * kEps0), e_per_n = kE / kEps0 * a.dx;
     const double d_per_e = (a.mask & FK_PHYS_VX) ? -kE / kMe * a.dt / a.dvx : 0.0;   // Courant number per V/m
     auto field_at = [&](int k, double nk) {
-        double e = (a.mask & FK_PHYS_SELF_FIELD) ? e_wall - e_per_n * (run + 0.5 * nk) : 0.0;
+        double e = 0.0;
+        if (a.mask & FK_PHYS_SELF_FIELD)
+            e = (a.mask & FK_PHYS_NO_SPACE_CHARGE) ? e_wall : e_wall - e_per_n * (run + 0.5 * nk);
         e += a.ex_ext;
         a.ex[k] = e;
         const double d = d_per_e * e;
@@ -737,12 +769,15 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
         const bool x_on = a.mask & FK_PHYS_X;
         const bool see_on = x_on && (a.mask & FK_PHYS_SEE);
         const double g_pe = x_on ? pe * a.dv2 : 0.0;
-        const double g_see = see_on ? see * a.dv2 * (1.0 - a.r_refl) : 0.0;   // 1 - R_f of the arrivals induce SEE
+        const double g_see = see_on ? see * a.dv2 * (1.0 - a.r_refl - a.r_inel) : 0.0;   // 1 - R_f induce SEE
         const double g_top = x_on ? top * a.dv2 : 0.0;
+        // the emission shape carries the secondaries and the inelastically
+        // reflected electrons
+        const double g_shape = g_see + (x_on ? a.r_inel * g_pe : 0.0);
         double gscale = 0.0;
-        if (see_on) {
-            if (a.emission_norm == FK_EMIT_DISCRETE) gscale = zsum > 0.0 ? g_see / zsum : 0.0;
-            else gscale = g_see * emit_pref;
+        if (x_on) {
+            if (a.emission_norm == FK_EMIT_DISCRETE) gscale = zsum > 0.0 ? g_shape / zsum : 0.0;
+            else gscale = g_shape * emit_pref;
         }
         const double emitted = gscale * zsum + (x_on ? a.r_refl * g_pe : 0.0);
         const double n_total = total * a.dx;
@@ -750,7 +785,7 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
         double resid = 0.0;
         if (a.advance) {
             const double inj = (a.mask & FK_PHYS_SRC) ? inj_step : 0.0;
-            resid = (n_total - old.n_total) - (a.dt * (old.emitted - old.g_pe - old.g_top) + inj - loss_v);
+            resid = (n_total - old.n_total) - (a.dt * (old.emitted - g_abs - top_abs) + inj - loss_v);
         }
         DevState ns = old;
         ns.step = old.step + (a.advance ? 1 : 0);

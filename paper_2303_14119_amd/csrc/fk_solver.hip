@@ -12,6 +12,7 @@
 
 #include "fk_kernels.h"
 #include "fk_sweep_fast.h"
+#include "fk_sweep2.h"
 
 namespace fk {
 
@@ -259,6 +260,7 @@ struct fk_ctx {
     std::vector<hipEvent_t> spare;
     std::vector<int> tile_order;   // host copy of the tile list (kept alive for the async upload)
     bool batch_member = false;     // stepped by a batch, not by fk_step
+    int64_t host_step = 0;         // step counter of the state, as the queued work will leave it
 };
 
 namespace {
@@ -295,6 +297,7 @@ SweepArgs<T> sweep_args(const fk_ctx* c, int from)
     a.part_wall = c->b.part_wall;
     a.part_top = c->b.part_top;
     a.part_lv = c->b.part_lv;
+    a.part_abs = c->b.part_abs;
     a.nx = c->p.nx;
     a.nvx = c->p.nvx;
     a.nvy = c->p.nvy;
@@ -342,8 +345,35 @@ void launch_sweep_t(const fk_ctx* c, int from, hipStream_t s)
     else launch_sweep_b<T, TI, MAXB, false>(c, from, s);
 }
 
-void launch_sweep(const fk_ctx* c, int from, hipStream_t s)
+template <typename T, int TI, int MAXB>
+void launch_sweep2_t(const fk_ctx* c, int from, hipStream_t s, int rev)
 {
+    SweepArgs<T> a = sweep_args<T>(c, from);
+    if (rev)
+        hipLaunchKernelGGL((k_sweep2<T, TI, MAXB, true>), dim3(c->L.nwg), dim3(c->L.block), c->L.lds_sweep, s, a);
+    else
+        hipLaunchKernelGGL((k_sweep2<T, TI, MAXB, false>), dim3(c->L.nwg), dim3(c->L.block), c->L.lds_sweep, s, a);
+}
+
+// second-order scheme: forward order on even steps, reversed on odd ones
+void launch_sweep2(const fk_ctx* c, int from, hipStream_t s, int rev)
+{
+    const bool small = c->L.block <= 512;
+    if (c->L.elem == 4) {
+        if (c->L.ti == 8) launch_sweep2_t<float, 8, 512>(c, from, s, rev);
+        else small ? launch_sweep2_t<float, 4, 512>(c, from, s, rev) : launch_sweep2_t<float, 4, 1024>(c, from, s, rev);
+    } else {
+        if (c->L.ti == 8) launch_sweep2_t<double, 8, 512>(c, from, s, rev);
+        else launch_sweep2_t<double, 4, 512>(c, from, s, rev);
+    }
+}
+
+void launch_sweep(const fk_ctx* c, int from, hipStream_t s, int rev = 0)
+{
+    if (c->L.scheme == FK_SCHEME_LIMITED2) {
+        launch_sweep2(c, from, s, rev);
+        return;
+    }
     const bool small = c->L.block <= 512;
     if (c->L.elem == 4) {
         switch (c->L.ti) {
@@ -408,6 +438,9 @@ FieldArgs field_args(const fk_ctx* c, int advance)
     a.dvx = c->L.dvx;
     a.ex_ext = c->p.ex_external;
     a.r_refl = c->p.r_refl;
+    a.r_inel = c->p.r_inel;
+    a.part_abs = c->b.part_abs;
+    a.abs_from_sweep = 0;
     if (c->L.bgk) {
         // Eq 4: nu_ee = n_e e^4 ln(Lambda) / (12 pi^1.5 eps0^2 sqrt(m_e) T_e^1.5), T_e in joules
         const double te = c->p.t_e_ev * kE;
@@ -417,7 +450,7 @@ FieldArgs field_args(const fk_ctx* c, int advance)
     return a;
 }
 
-void launch_field(const fk_ctx* c, int advance, hipStream_t s)
+void launch_field(const fk_ctx* c, int advance, hipStream_t s, int rev = 0)
 {
     // many narrow workgroups for the plane sums (the bulk of the reduction),
     // then the one-workgroup field solve on them
@@ -425,14 +458,21 @@ void launch_field(const fk_ctx* c, int advance, hipStream_t s)
                        c->b.plane_sum);
     FieldArgs a = field_args(c, advance);
     a.plane_sum = c->b.plane_sum;
+    a.abs_from_sweep = (advance && rev) ? 1 : 0;
     hipLaunchKernelGGL(k_field, dim3(1), dim3(kFieldThreads), 0, s, a);
 }
 
-// one step from buffer `from` into the other
-void enqueue_step(const fk_ctx* c, int from, hipStream_t s)
+// whether step `step` (from f^step) runs in the reversed split order
+int reversed_step(const fk_ctx* c, int64_t step)
 {
-    launch_sweep(c, from, s);
-    launch_field(c, 1, s);
+    return (c->L.scheme == FK_SCHEME_LIMITED2 && (step & 1)) ? 1 : 0;
+}
+
+// one step from buffer `from` into the other
+void enqueue_step(const fk_ctx* c, int from, hipStream_t s, int rev = 0)
+{
+    launch_sweep(c, from, s, rev);
+    launch_field(c, 1, s, rev);
 }
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
@@ -451,10 +491,11 @@ int upload_tiles(fk_ctx* c)
     return FK_OK;
 }
 
-int alloc_buffers(fk_ctx* c, void* fa, void* fb)
+// Layout of an instance's tables, partials and small state in one block of
+// device memory (everything but f); returns its size in bytes and, with a
+// base address, points b's members into it.
+size_t carve_buffers(const fk_params& p, const Layout& L, char* base, Buffers* b)
 {
-    const fk_params& p = c->p;
-    const Layout& L = c->L;
     const size_t v2 = (size_t)p.nvx * p.nvy;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
@@ -462,39 +503,50 @@ int alloc_buffers(fk_ctx* c, void* fa, void* fb)
                  o_fsrc = take(v2 * L.elem), o_wband = take(p.nx * 8), o_srck = take(p.nx * 8),
                  o_pn = take((size_t)p.nx * L.n_it_cap * 8), o_pw = take((size_t)L.n_it_cap * 16),
                  o_pt = take((size_t)L.n_it_cap * 8), o_plv = take((size_t)L.nwg_cap * 8),
+                 o_pab = take((size_t)L.n_it_cap * 16),
                  o_ne = take(p.nx * 8), o_ex = take(p.nx * 8), o_dxk = take(p.nx * 8),
                  o_nudt = take(p.nx * 8), o_nudtn = take(p.nx * 8), o_gx = take((size_t)p.nvx * L.elem),
                  o_gy = take((size_t)p.nvy * L.elem),
                  o_consts = take(64), o_tiles = take((size_t)L.n_it_cap * sizeof(int)),
                  o_psum = take((size_t)p.nx * 8), o_st = take(sizeof(DevState)),
                  o_ring = take((size_t)p.trace_cap * sizeof(fk_state));
+    if (!base) return off;
+    b->delta = (double*)(base + o_delta);
+    b->ghat = (double*)(base + o_ghat);
+    b->fsrc64 = (double*)(base + o_fsrc64);
+    b->fsrc = base + o_fsrc;
+    b->wband = (double*)(base + o_wband);
+    b->srck = (double*)(base + o_srck);
+    b->part_n = (double*)(base + o_pn);
+    b->part_wall = (double*)(base + o_pw);
+    b->part_top = (double*)(base + o_pt);
+    b->part_lv = (double*)(base + o_plv);
+    b->part_abs = (double*)(base + o_pab);
+    b->ne = (double*)(base + o_ne);
+    b->ex = (double*)(base + o_ex);
+    b->dxk = (double*)(base + o_dxk);
+    b->nudt = (double*)(base + o_nudt);
+    b->nudt_n = (double*)(base + o_nudtn);
+    b->gx = base + o_gx;
+    b->gy = base + o_gy;
+    b->consts = (double*)(base + o_consts);
+    b->tiles = (int*)(base + o_tiles);
+    b->plane_sum = (double*)(base + o_psum);
+    b->st = (DevState*)(base + o_st);
+    b->ring = (fk_state*)(base + o_ring);
+    return off;
+}
+
+int alloc_buffers(fk_ctx* c, void* fa, void* fb)
+{
+    const fk_params& p = c->p;
+    const Layout& L = c->L;
+    const size_t off = carve_buffers(p, L, nullptr, nullptr);
     if (hipMalloc(&c->pool, off) != hipSuccess) {
         c->pool = nullptr;
         return set_error(&c->err, FK_E_OOM, "device allocation of tables and partials failed");
     }
-    char* base = static_cast<char*>(c->pool);
-    c->b.delta = (double*)(base + o_delta);
-    c->b.ghat = (double*)(base + o_ghat);
-    c->b.fsrc64 = (double*)(base + o_fsrc64);
-    c->b.fsrc = base + o_fsrc;
-    c->b.wband = (double*)(base + o_wband);
-    c->b.srck = (double*)(base + o_srck);
-    c->b.part_n = (double*)(base + o_pn);
-    c->b.part_wall = (double*)(base + o_pw);
-    c->b.part_top = (double*)(base + o_pt);
-    c->b.part_lv = (double*)(base + o_plv);
-    c->b.ne = (double*)(base + o_ne);
-    c->b.ex = (double*)(base + o_ex);
-    c->b.dxk = (double*)(base + o_dxk);
-    c->b.nudt = (double*)(base + o_nudt);
-    c->b.nudt_n = (double*)(base + o_nudtn);
-    c->b.gx = base + o_gx;
-    c->b.gy = base + o_gy;
-    c->b.consts = (double*)(base + o_consts);
-    c->b.tiles = (int*)(base + o_tiles);
-    c->b.plane_sum = (double*)(base + o_psum);
-    c->b.st = (DevState*)(base + o_st);
-    c->b.ring = (fk_state*)(base + o_ring);
+    carve_buffers(p, L, static_cast<char*>(c->pool), &c->b);
     FK_HIP(c, hipMemsetAsync(c->pool, 0, off, c->stream));
     {
         int rc = upload_tiles(c);
@@ -583,7 +635,7 @@ int capture_graphs(fk_ctx* c)
     for (int start = 0; start < 2; ++start) {
         hipGraph_t g = nullptr;
         FK_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
-        for (int s = 0; s < c->graph_steps; ++s) enqueue_step(c, (start + s) & 1, c->cap_stream);
+        for (int s = 0; s < c->graph_steps; ++s) enqueue_step(c, (start + s) & 1, c->cap_stream, reversed_step(c, s));
         hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
         if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
         e = hipGraphInstantiate(&c->graph[start], g, nullptr, nullptr, 0);
@@ -738,8 +790,25 @@ int sweep_wgs_per_cu_b(const Layout& L)
     return e == hipSuccess ? occ : 0;
 }
 
+int sweep2_wgs_per_cu(const Layout& L)
+{
+    int occ = 0;
+    hipError_t e;
+    const bool small = L.block <= 512;
+    if (L.elem == 4) {
+        if (L.ti == 8) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sweep2<float, 8, 512, false>, L.block, L.lds_sweep);
+        else if (small) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sweep2<float, 4, 512, false>, L.block, L.lds_sweep);
+        else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sweep2<float, 4, 1024, false>, L.block, L.lds_sweep);
+    } else {
+        if (L.ti == 8) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sweep2<double, 8, 512, false>, L.block, L.lds_sweep);
+        else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_sweep2<double, 4, 512, false>, L.block, L.lds_sweep);
+    }
+    return e == hipSuccess ? occ : 0;
+}
+
 int sweep_wgs_per_cu(const Layout& L)
 {
+    if (L.scheme == FK_SCHEME_LIMITED2) return sweep2_wgs_per_cu(L);
     return L.bgk ? sweep_wgs_per_cu_b<true>(L) : sweep_wgs_per_cu_b<false>(L);
 }
 
@@ -870,39 +939,49 @@ extern "C" int fk_step(fk_ctx* c, int64_t n)
     if (!c || n < 0) return set_error(c ? &c->err : nullptr, FK_E_INVALID, "bad arguments to fk_step");
     if (c->batch_member) return set_error(&c->err, FK_E_STATE, "a batch member is stepped through fk_batch_step");
     if (c->sticky) return c->sticky;
+    auto direct = [&]() {
+        enqueue_step(c, c->cur, c->stream, reversed_step(c, c->host_step));
+        c->cur ^= 1;
+        c->host_step += 1;
+    };
     if (c->prof) {
         // direct launches; a sampled step gets three events: before and
         // after its sweep launch and after its reduction and field kernels
         for (int64_t s = 0; s < n; ++s) {
             if (c->prof_count++ % c->prof != 0) {
-                enqueue_step(c, c->cur, c->stream);
-                c->cur ^= 1;
+                direct();
                 continue;
             }
             hipEvent_t e0 = get_event(c), e1 = get_event(c), e2 = get_event(c);
             if (!e0 || !e1 || !e2) return set_error(&c->err, FK_E_HIP, "hipEventCreate failed");
+            const int rev = reversed_step(c, c->host_step);
             FK_HIP(c, hipEventRecord(e0, c->stream));
-            launch_sweep(c, c->cur, c->stream);
+            launch_sweep(c, c->cur, c->stream, rev);
             FK_HIP(c, hipEventRecord(e1, c->stream));
-            launch_field(c, 1, c->stream);
+            launch_field(c, 1, c->stream, rev);
             FK_HIP(c, hipEventRecord(e2, c->stream));
             c->events.push_back({e0, e1, e2});
             c->cur ^= 1;
+            c->host_step += 1;
         }
         FK_HIP(c, hipGetLastError());
         return FK_OK;
     }
     int64_t left = n;
+    // the graphs start at an even step (the second-order scheme alternates
+    // its split order with the step's parity)
+    if (left > 0 && (c->host_step & 1) && c->L.scheme == FK_SCHEME_LIMITED2) {
+        direct();
+        left -= 1;
+    }
     if (c->graph_ready) {
         while (left >= c->graph_steps) {
             FK_HIP(c, hipGraphLaunch(c->graph[c->cur], c->stream));
-            left -= c->graph_steps;   // graph_steps is even: cur unchanged
+            left -= c->graph_steps;   // graph_steps is even: cur and the step parity unchanged
+            c->host_step += c->graph_steps;
         }
     }
-    for (; left > 0; --left) {
-        enqueue_step(c, c->cur, c->stream);
-        c->cur ^= 1;
-    }
+    for (; left > 0; --left) direct();
     FK_HIP(c, hipGetLastError());
     return FK_OK;
 }
@@ -1003,6 +1082,7 @@ extern "C" int fk_write_state(fk_ctx* c, const void* f, int on_device, double si
     if (rc) return rc;
     FK_HIP(c, hipStreamSynchronize(c->stream));
     c->sticky = FK_OK;
+    c->host_step = step;
     c->history.clear();
     c->drained_step = step - 1;
     // the record of the restored state itself is drained from the ring only
@@ -1070,6 +1150,7 @@ extern "C" int fk_autotune(fk_ctx* c, int trial_steps, fk_info* chosen)
     DevState saved;
     rc = read_devstate(c, &saved);
     if (rc) return rc;
+    const int64_t saved_step = c->host_step;
     // keep the state while the trials step it
     const size_t fbytes = (size_t)c->L.cells * c->L.elem;
     void* keep = nullptr;
@@ -1116,6 +1197,7 @@ extern "C" int fk_autotune(fk_ctx* c, int trial_steps, fk_info* chosen)
         rc = FK_E_HIP;
     }
     if (hipMemcpyAsync(c->b.st, &saved, sizeof(saved), hipMemcpyHostToDevice, c->stream) != hipSuccess && !rc) rc = FK_E_HIP;
+    c->host_step = saved_step;
     if (!rc) rc = refresh(c);
     if (!rc) FK_HIP(c, hipStreamSynchronize(c->stream));
     c->prof = prof;
@@ -1521,6 +1603,8 @@ extern "C" int fk_batch_create(const fk_params* params, int n, void* stream, int
         if (rc) return set_error(nullptr, rc, "instance " + std::to_string(m) + ": " + why);
         if (params[m].dtype != FK_F32) return set_error(nullptr, FK_E_INVALID, "batched instances are FK_F32");
         if (L.block > kBatchThreads) return set_error(nullptr, FK_E_INVALID, "batched instances need nvy <= 256");
+        if (params[m].scheme != FK_SCHEME_UPWIND)
+            return set_error(nullptr, FK_E_INVALID, "batched instances take the first-order scheme");
     }
     fk_batch* b = new (std::nothrow) fk_batch();
     if (!b) return set_error(nullptr, FK_E_OOM, "host allocation failed");

@@ -58,11 +58,14 @@ def bad(**kw):
 @pytest.mark.parametrize("kw,code", [
     (dict(nx=0), fk.E_INVALID), (dict(nvy=1025), fk.E_INVALID), (dict(length=-1.0), fk.E_INVALID),
     (dict(t_se_ev=0.0), fk.E_INVALID), (dict(x_src_lo=2e-5, x_src_hi=1e-5), fk.E_INVALID),
-    (dict(physics_mask=128), fk.E_INVALID), (dict(emission_norm=2), fk.E_INVALID),
+    (dict(physics_mask=256), fk.E_INVALID), (dict(emission_norm=2), fk.E_INVALID),
     (dict(physics_mask=W.ALL | W.BGK, t_e_ev=0.0), fk.E_INVALID),
     (dict(physics_mask=W.BGK, ln_lambda=0.0), fk.E_INVALID),
     (dict(physics_mask=W.BGK, t_e_ev=float("inf")), fk.E_INVALID),
     (dict(r_refl=-0.1), fk.E_INVALID), (dict(r_refl=1.5), fk.E_INVALID), (dict(r_refl=float("nan")), fk.E_INVALID),
+    (dict(r_inel=-0.1), fk.E_INVALID), (dict(r_refl=0.6, r_inel=0.5), fk.E_INVALID),
+    (dict(r_inel=float("nan")), fk.E_INVALID), (dict(scheme=2), fk.E_INVALID), (dict(scheme=-1), fk.E_INVALID),
+    (dict(scheme=1, physics_mask=W.ALL | W.BGK), fk.E_INVALID),
     (dict(tile_rows=3), fk.E_INVALID), (dict(trace_cap=0), fk.E_INVALID),
     (dict(dt=1e-11), fk.E_CFL), (dict(ey=-1e9, dt=3e-13), fk.E_CFL),
 ])
@@ -71,13 +74,27 @@ def test_validate_rejects(kw, code):
     assert fk.fk_last_error(None)
 
 
-def test_width_limits_per_precision():
+@pytest.mark.parametrize("nx", [4, 64, 2048])
+@pytest.mark.parametrize("mask", [W.ALL, W.ALL | W.BGK])
+def test_width_limits_per_precision(nx, mask):
     """nvy up to 1024 in FP32, up to 960 in FP64 (the tile's v_y exchange
-    must fit in 64 KB of LDS)."""
+    must fit in 64 KB of LDS), at any x extent and with the collision term
+    (the default x run shrinks to as few as 4 planes to leave room)."""
     for nvy, dtype, code in ((1024, "f32", fk.OK), (960, "f64", fk.OK), (1024, "f64", fk.E_INVALID)):
-        cfg = W.config(nx=4, nvx=6, nvy=nvy, length=1e-5, ey=-4e6, delta_max=2.5, a_max_ev=400.0, cfl=0.8)
+        cfg = W.config(nx=nx, nvx=6, nvy=nvy, length=1e-5 * nx / 4, ey=-4e6, delta_max=2.5, a_max_ev=400.0,
+                       cfl=0.8, physics_mask=mask)
         p = fk.make_params(cfg, dtype)
         assert fk.fk_validate(C.byref(p), None) == code, (nvy, dtype)
+
+
+def test_new_physics_parameters_are_accepted():
+    """The inelastic share, the no-space-charge bit and the second-order
+    scheme validate within their ranges."""
+    for kw in (dict(r_refl=0.4, r_inel=0.6), dict(r_inel=1.0), dict(physics_mask=W.ALL | W.NOSC),
+               dict(scheme=1), dict(scheme=1, r_refl=0.2, r_inel=0.1)):
+        for dtype in ("f32", "f64"):
+            p = fk.make_params(dict(W.c0(), **kw), dtype)
+            assert fk.fk_validate(C.byref(p), None) == fk.OK, kw
 
 
 def test_tile_rows_rule_and_limits():
@@ -138,6 +155,8 @@ def test_batch_rejects_before_touching_the_gpu():
         assert fk.fk_batch_create(arr, len(cfgs), None, 0, C.byref(h)) == fk.E_INVALID
         assert not h.value
         assert fk.fk_batch_last_error(None)
+    arr = (fk.fk_params * 1)(fk.make_params(dict(good, scheme=1), "f32"))
+    assert fk.fk_batch_create(arr, 1, None, 0, C.byref(C.c_void_p())) == fk.E_INVALID
     arr = (fk.fk_params * 1)(fk.make_params(good, "f32"))
     assert fk.fk_batch_create(arr, 0, None, 0, C.byref(C.c_void_p())) == fk.E_INVALID
     assert fk.fk_batch_create(arr, 1, None, 4, C.byref(C.c_void_p())) == fk.E_INVALID

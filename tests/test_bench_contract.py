@@ -20,15 +20,16 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2 and "one GPU" in r.stderr
 
 
-def test_traffic_digest_is_read_from_the_profile():
+@pytest.mark.parametrize("workload,lo,hi", [("c1", 1.0e9, 1.3e9), ("c4", 4.5e9, 5.8e9)])
+def test_traffic_digest_is_read_from_the_profile(workload, lo, hi):
     sys.path.insert(0, ROOT)
     import bench
     d = bench.kernel_source_digest()
     assert len(d) == 16
-    text = open(os.path.join(ROOT, "profiles", "sweep_c1_rocprof.md")).read()
-    t = bench.measured_traffic()
-    if ("kernel_source_digest: " + d) in text:
-        assert t is not None and 1.0e9 < t < 1.3e9
+    text = open(bench.PROFILE_SUMMARY[workload]).read()
+    t = bench.measured_traffic(workload)
+    if ("kernel_source_digest: " + d) in text and "hbm_bytes_per_launch" in text:
+        assert t is not None and lo < t < hi
     else:
         assert t is None
 
@@ -46,4 +47,6 @@ def test_short_bench_prints_the_contract_line():
     assert KEYS <= set(out) and ROOFLINE_KEYS <= set(out["roofline"])
     assert out["n_gpus"] == 1 and out["steps"] == 20 and out["value"] > 0
     assert out["roofline"]["bound"] == "hbm" and 0 < out["roofline"]["frac"] < 1
-    assert out["config"]["workload"].startswith("plain single run, 2048x256x256")
+    assert out["config"]["workload"].startswith("plain single run, 4096x384x384")
+    # a short run times every step's sweep
+    assert out["roofline"]["timed_launches"] == 20 and out["roofline"]["sample_every"] == 1

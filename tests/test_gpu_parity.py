@@ -97,6 +97,7 @@ def test_c0_fp32_full_run(fk):
         worst = max(rel(g["sigma"] + g["sigma_lo"], r["sigma"]) for g, r in zip(gtr[1:], otr)
                     if abs(r["sigma"]) > 1e-3 * abs(orc["sigma"]))
         print("C0 fp32 worst sigma error along the trace:", worst)
+        assert worst <= 1e-6
 
 
 RAGGED = [
