@@ -250,6 +250,31 @@ int fk_read_profile(fk_ctx* ctx, int npts, double* out, int dst_on_device);
  * fk_write_state. */
 int fk_warm_start(fk_ctx* ctx, const double* profile, int npts, int src_on_device, double t_ev, int64_t step);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the work of
+ * fk_create_borrowed + fk_write_state + fk_step(nsteps) + fk_read_state in
+ * one call that allocates nothing.  f_a and f_b are the caller's two device
+ * buffers of nx*nvx*nvy elements (type of p->dtype); f_a holds f^0 on entry
+ * and both are overwritten; after the call the state is in f_a if nsteps is
+ * even, in f_b if odd.  sigma + sigma_lo and step give the starting surface
+ * charge and step counter.  state_out (device memory, may be NULL) receives
+ * the observables of the final state as fk_read_state gives them, and
+ * flags_out (device, may be NULL) its flags: bit 0 a Courant number above
+ * one, bit 1 a non-finite moment (what fk_sync turns into FK_E_CFL /
+ * FK_E_NONFINITE).  The work is queued on stream and the call returns
+ * without waiting; results are the same, bit for bit, as with a context.
+ * Tables, tile partials, the small state and the trace ring (trace_cap
+ * records; they are not read back) live in a file-scope array of 32 MiB per
+ * GPU that the library holds until the process ends; parameters needing more
+ * (in practice nx * ceil(nvx/4) * 8 bytes of partials plus 32 bytes per
+ * velocity cell of tables) fail with FK_E_INVALID.  Every call on a GPU
+ * shares that array and the call clears what it uses first: calls that
+ * overlap on one GPU (other streams or threads) race and give wrong results.
+ * Errors: FK_E_INVALID for bad arguments or parameters, FK_E_HIP for a failed
+ * launch; fk_last_error(NULL) gives the message. */
+int fk_step_noalloc(const fk_params* p, void* stream, void* f_a, void* f_b, double sigma, double sigma_lo,
+                    int64_t step, int64_t nsteps, fk_state* state_out, uint32_t* flags_out);
+
 /* Saturation test of Section 2 (sigma, Gamma_pe and Gamma_see each change
  * by at most rtol relative within a window of window_s seconds), applied to
  * the trace history drained so far (the call drains the ring first).

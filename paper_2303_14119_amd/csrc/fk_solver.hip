@@ -6,6 +6,7 @@
 // wall partials, updates sigma and prepares the next step.  Steps are
 // replayed from captured HIP graphs.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -1203,6 +1204,143 @@ extern "C" int fk_autotune(fk_ctx* c, int trial_steps, fk_info* chosen)
     c->prof = prof;
     if (rc) return rc;
     if (chosen) return fk_query(c, chosen);
+    return FK_OK;
+}
+
+// ================================================================ no allocation
+//
+// fk_step_noalloc: borrowed create, steps and state read-out in one call
+// that allocates nothing.  Everything but f (tables, tile partials, the
+// small state, the trace ring) lives in one file-scope device array per
+// GPU; the caller's two f buffers hold the state.
+
+namespace fk {
+
+constexpr size_t kScratchBytes = (size_t)32 << 20;   // 32 MiB per device, held until the process ends
+constexpr int kMaxDevices = 64;
+
+__device__ __align__(256) char scratch[kScratchBytes];
+
+__global__ void k_fill_zero(uint64_t* __restrict__ p, size_t n)
+{
+    for (size_t m = (size_t)blockIdx.x * blockDim.x + threadIdx.x; m < n; m += (size_t)gridDim.x * blockDim.x)
+        p[m] = 0;
+}
+
+// the v_x tile list of a layout (fast tiles first, then the others), made
+// on the device so that no host buffer has to outlive the call
+__global__ void k_tile_list(int* __restrict__ tiles, int n_it, int ti, int nvx)
+{
+    if (threadIdx.x != 0) return;
+    int m = 0;
+    for (int it = 0; it < n_it; ++it)
+        if (tile_is_fast(it, ti, nvx)) tiles[m++] = it;
+    for (int it = 0; it < n_it; ++it)
+        if (!tile_is_fast(it, ti, nvx)) tiles[m++] = it;
+}
+
+__global__ void k_state_init(DevState* __restrict__ st, double sigma, double sigma_lo, int64_t step)
+{
+    if (threadIdx.x != 0) return;
+    DevState s{};
+    s.step = step;
+    s.sigma = sigma;
+    s.sigma_lo = sigma_lo;
+    *st = s;
+}
+
+__global__ void k_state_out(const DevState* __restrict__ st, double dt, fk_state* __restrict__ out,
+                            uint32_t* __restrict__ flags)
+{
+    if (threadIdx.x != 0) return;
+    const DevState s = *st;
+    if (out) {
+        fk_state r;
+        r.step = s.step;
+        r.t = (double)s.step * dt;
+        r.sigma = s.sigma;
+        r.sigma_lo = s.sigma_lo;
+        r.g_pe = s.g_pe;
+        r.g_see = s.g_see;
+        r.g_top = s.g_top;
+        r.emitted = s.emitted;
+        r.loss_v = s.loss_v;
+        r.n_total = s.n_total;
+        r.resid = s.resid;
+        *out = r;
+    }
+    if (flags) *flags = s.flags;
+}
+
+}  // namespace fk
+
+namespace {
+
+// device address of the scratch array on each device, taken once per device
+// with that device current
+std::atomic<void*> g_scratch_addr[fk::kMaxDevices];
+
+void* scratch_address(int dev)
+{
+    if (dev < 0 || dev >= fk::kMaxDevices) return nullptr;
+    void* p = g_scratch_addr[dev].load(std::memory_order_acquire);
+    if (p) return p;
+    void* q = nullptr;
+    if (hipGetSymbolAddress(&q, HIP_SYMBOL(fk::scratch)) != hipSuccess || !q) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    g_scratch_addr[dev].store(q, std::memory_order_release);
+    return q;
+}
+
+}  // namespace
+
+extern "C" int fk_step_noalloc(const fk_params* p, void* stream, void* f_a, void* f_b, double sigma,
+                               double sigma_lo, int64_t step, int64_t nsteps, fk_state* state_out,
+                               uint32_t* flags_out)
+{
+    if (!p || !f_a || !f_b || f_a == f_b || nsteps < 0 || step < 0 || !std::isfinite(sigma) || !std::isfinite(sigma_lo))
+        return set_static_error(FK_E_INVALID, "fk_step_noalloc: bad arguments");
+    Layout L;
+    int rc = derive_layout(p, &L, nullptr);
+    if (rc) return set_static_error(rc, "fk_step_noalloc: invalid parameters (fk_validate gives the reason)");
+    if (p->tile_planes == 0) choose_planes(p, &L);
+    const size_t need = carve_buffers(*p, L, nullptr, nullptr);
+    if (need > kScratchBytes)
+        return set_static_error(FK_E_INVALID,
+                                "fk_step_noalloc: tables, partials and trace ring need more than the 32 MiB scratch "
+                                "(fewer x planes, velocity cells or trace records)");
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return set_static_error(FK_E_HIP, "fk_step_noalloc: hipGetDevice failed");
+    void* base = scratch_address(dev);
+    if (!base) return set_static_error(FK_E_HIP, "fk_step_noalloc: hipGetSymbolAddress of the scratch array failed");
+
+    // a context on the stack: members that own memory stay empty
+    fk_ctx c;
+    c.p = *p;
+    c.L = L;
+    c.stream = static_cast<hipStream_t>(stream);
+    c.own_f = false;
+    c.b.f[0] = f_a;
+    c.b.f[1] = f_b;
+    carve_buffers(*p, L, static_cast<char*>(base), &c.b);
+    hipStream_t s = c.stream;
+    // clear the part of the array this call uses (earlier calls leave their
+    // contents): a fill kernel, as callers may capture the call in a graph
+    const size_t words = (need + 7) / 8;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)std::min<size_t>((words + 255) / 256, 2048)), dim3(256), 0, s,
+                       static_cast<uint64_t*>(base), words);
+    hipLaunchKernelGGL(k_tile_list, dim3(1), dim3(64), 0, s, c.b.tiles, L.n_it, L.ti, p->nvx);
+    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, c.b.st, sigma, sigma_lo, step);
+    if (hipGetLastError() != hipSuccess) return set_static_error(FK_E_HIP, "fk_step_noalloc: a set-up launch failed");
+    if (build_tables(&c) || refresh(&c)) return set_static_error(FK_E_HIP, "fk_step_noalloc: a set-up launch failed");
+    for (int64_t n = 0; n < nsteps; ++n) {
+        enqueue_step(&c, c.cur, s, reversed_step(&c, step + n));
+        c.cur ^= 1;
+    }
+    hipLaunchKernelGGL(k_state_out, dim3(1), dim3(64), 0, s, c.b.st, L.dt, state_out, flags_out);
+    if (hipGetLastError() != hipSuccess) return set_static_error(FK_E_HIP, "fk_step_noalloc: a step launch failed");
     return FK_OK;
 }
 

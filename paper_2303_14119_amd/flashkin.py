@@ -116,6 +116,8 @@ SIGNATURES = {
     "fk_set_profiling": (C.c_int, [_ctx, C.c_int]),
     "fk_kernel_times": (C.c_int, [_ctx, _P(C.c_double), _P(C.c_int64), _P(C.c_double), _P(C.c_int64)]),
     "fk_autotune": (C.c_int, [_ctx, C.c_int, _P(fk_info)]),
+    "fk_step_noalloc": (C.c_int, [_P(fk_params), _vp, _vp, _vp, C.c_double, C.c_double, C.c_int64, C.c_int64,
+                                  _vp, _vp]),
     "fk_batch_create": (C.c_int, [_P(fk_params), C.c_int, _vp, C.c_int, _P(_vp)]),
     "fk_batch_destroy": (C.c_int, [_vp]),
     "fk_batch_step": (C.c_int, [_vp, C.c_int64]),
