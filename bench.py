@@ -35,13 +35,17 @@ PROFILE_SUMMARY = {"c1": os.path.join(ROOT, "profiles", "sweep_c1_rocprof.md"),
 
 
 def kernel_source_digest():
-    """Hash of the sweep kernel's device code and of the code that shapes
-    its launch (tile rows, planes, workgroup size), comments and whitespace
-    left out."""
+    """Hash of the first-order sweep kernel's device code and of the code
+    that shapes its launch (tile rows, planes, workgroup size, arguments:
+    the marked region of fk_solver.hip), comments and whitespace left out."""
     h = hashlib.sha256()
     for name in ("fk_internal.h", "fk_kernels.h", "fk_sweep_fast.h", "fk_host.cpp", "fk_solver.hip"):
         with open(os.path.join(ROOT, "paper_2303_14119_amd", "csrc", name), encoding="utf-8") as fh:
             text = fh.read()
+        if name == "fk_solver.hip":
+            a = text.index("// ---- sweep launch shape (begin)")
+            b = text.index("// ---- sweep launch shape (end)")
+            text = text[a:b]
         text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
         text = re.sub(r"//[^\n]*", " ", text)
         h.update(" ".join(text.split()).encode())
@@ -94,6 +98,45 @@ def cpu_baseline(cfg, budget_s=12.0, budget_1t_s=6.0):
                       f"oracle built with gcc -O3 -march=native on this host",
             "value_1_thread": cells * n1 / el1 / 1e9,
             "sample_1_thread": f"{n1} whole steps on 1 thread ({el1:.1f} s)"}
+
+
+WEIGHTS = os.path.join(ROOT, "paper_2303_14119_amd", "weights", "surrogate.npz")
+
+
+def time_to_saturation(cfg, stream, t_max=5e-9):
+    """The metric's second half: steps and wall time to the Section 2
+    saturation test (sigma, Gamma_pe and Gamma_see within 0.1% over 50 ps)
+    from the plain cold start and from the surrogate's warm start, on the
+    same GPU, and the relative L2 distance of the two final sigma_enc(x)
+    profiles (256 points)."""
+    import numpy as np
+    from paper_2303_14119_amd import flashkin as fk
+    from paper_2303_14119_amd import surrogate as S
+    if not os.path.exists(WEIGHTS):
+        return None
+    sur = S.Surrogate.from_file(WEIGHTS, stream=stream)
+    out, profiles = {}, {}
+    dt = fk.validate(fk.make_params(cfg))["dt"]
+    for mode in ("cold", "warm"):
+        with fk.Solver(cfg, "f32", stream=stream, trace_cap=8192, trace_stride=S.trace_stride(dt)) as s:
+            setup, why = 0.0, None
+            if mode == "warm":
+                t0 = time.perf_counter()
+                _, why = S.warm_start(s, cfg, sur)
+                setup = time.perf_counter() - t0
+            sat, steps, wall = S.time_to_saturation(s, t_max=t_max, check_steps=500)
+            st = s.state()
+            profiles[mode] = s.profile(S.NPTS)
+        out[mode] = {"saturated": bool(sat), "steps": steps, "sim_time_s": steps * dt, "wall_s": round(wall, 3),
+                     "setup_s": round(setup, 4), "sigma": st["sigma"] + st["sigma_lo"]}
+        if mode == "warm":
+            out[mode]["fallback"] = why
+    d = profiles["warm"] - profiles["cold"]
+    out["final_sigma_enc_rel_l2"] = float(np.linalg.norm(d) / np.linalg.norm(profiles["cold"]))
+    out["wall_speedup"] = round(out["cold"]["wall_s"] / (out["warm"]["wall_s"] + out["warm"]["setup_s"]), 3)
+    h = hashlib.sha256(open(WEIGHTS, "rb").read()).hexdigest()[:16]
+    out["weights"] = f"paper_2303_14119_amd/weights/surrogate.npz sha256 {h}"
+    return out
 
 
 def bench_batch(args):
@@ -175,6 +218,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-tts", action="store_true",
+                    help="skip the time-to-saturation comparison (cold start vs surrogate warm start, 4096x384x384)")
     ap.add_argument("--batch-default", action="store_true",
                     help="batch mode: the default tiling and launch mode instead of the autotuned choice")
     ap.add_argument("--sample-every", type=int, default=0,
@@ -192,6 +237,11 @@ def main():
                     help="with the electron-electron collision term (Eq 3-5, T_e 2 eV, ln Lambda 10), "
                          "starting from a thin Maxwellian background in every x plane so that every "
                          "plane takes the term")
+    ap.add_argument("--second-order", action="store_true",
+                    help="the second-order limited scheme (FK_SCHEME_LIMITED2, an accuracy extension beyond the "
+                         "paper) instead of the paper's first-order upwind step")
+    ap.add_argument("--tile-rows", type=int, default=0, help="v_x rows per tile (0: the library's choice)")
+    ap.add_argument("--tile-planes", type=int, default=0, help="x planes per tile (0: the library's choice)")
     ap.add_argument("--mode", choices=("c1", "batch", "mlp"), default="c1",
                     help="c1: the headline line (default); batch: the 64-instance batched sweep; "
                          "mlp: surrogate training steps (both for profiling, one JSON line each)")
@@ -220,6 +270,8 @@ def main():
         cfg = dict(c4, nx=c4["nx"] // 8, length=c4["length"] / 8)
     if args.bgk:
         cfg = dict(cfg, physics_mask=W.ALL | W.BGK, t_e_ev=2.0, ln_lambda=10.0)
+    if args.second_order:
+        cfg = dict(cfg, scheme=1)
     dev = torch.device("cuda:0")
     torch.cuda.init()
     if args.calib_copy:
@@ -231,7 +283,8 @@ def main():
         torch.cuda.synchronize()
         del a, b
     stream = torch.cuda.current_stream().cuda_stream
-    s = fk.Solver(cfg, "f32", stream=stream, trace_cap=64, trace_stride=1000)
+    s = fk.Solver(cfg, "f32", stream=stream, trace_cap=64, trace_stride=1000, tile_rows=args.tile_rows,
+                  tile_planes=args.tile_planes)
     cells = s.info["cells"]
     if args.bgk:
         # background of 1e12 electrons per m^3 in every plane (a Maxwellian at
@@ -281,7 +334,7 @@ def main():
     field_ms = kt["field_ms"] / max(kt["field_n"], 1)
     bytes_per_launch = 8.0 * cells
     achieved = bytes_per_launch / (sweep_ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload) if not args.bgk else None
+    traffic = measured_traffic(args.workload) if not (args.bgk or args.second_order) else None
     out = {
         "metric": "Gcell-updates/s",
         "value": round(value, 3),
@@ -302,21 +355,27 @@ def main():
                                 f"|E_y| {abs(cfg['ey']) / 1e6:g} MV/m, delta_max {cfg['delta_max']:g}, "
                                 f"A_max {cfg['a_max_ev']:g} eV, FP32 f, FP64 sigma and fluxes"
                                 + (", with e-e collisions (BGK, T_e 2 eV) from a 1e12 m^-3 background"
-                                   if args.bgk else "")),
+                                   if args.bgk else "")
+                                + (", second-order limited scheme (alternating split order)"
+                                   if args.second_order else "")),
                    "nx": cfg["nx"], "nvx": cfg["nvx"], "nvy": cfg["nvy"], "cells": cells,
+                   "tile_rows": s.info["tile_rows"], "tile_planes": s.info["tile_planes"],
                    "dt_s": s.dt, "step_start": st["step"] - 2 * args.steps,
                    "sigma_at_end": st["sigma"] + st["sigma_lo"],
                    "graph_replay_value": round(cells * args.steps / (g1 - g0) / 1e9, 3)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "kernel": "k_sweep (fused x/v_x/v_y upwind + source + moments)",
+                     "kernel": ("k_sweep2 (fused limited x/v_x/v_y + source + moments, both split orders)"
+                                if args.second_order else "k_sweep (fused x/v_x/v_y upwind + source + moments)"),
                      "kernel_ms": round(sweep_ms, 5), "reduce_field_interval_ms": round(field_ms, 5),
                      "timed_launches": kt["sweep_n"], "sample_every": args.sample_every,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
         "cpu_baseline": None,
     }
-    if not args.no_cpu and args.workload in ("c1", "c4") and not args.bgk:
+    if not args.no_tts and args.workload == "c4" and not (args.bgk or args.second_order):
+        out["time_to_saturation"] = time_to_saturation(cfg, stream)
+    if not args.no_cpu and args.workload in ("c1", "c4") and not (args.bgk or args.second_order):
         out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out), flush=True)
 

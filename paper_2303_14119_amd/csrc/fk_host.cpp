@@ -142,8 +142,9 @@ int derive_layout(const fk_params* p, Layout* L, std::string* why)
         l.kc = kc;
         l.n_kc = (p->nx + kc - 1) / kc;
         l.nwg = l.n_it * l.n_kc;
-        l.n_fast = l.n_it;
-        l.n_generic = 0;
+        l.n_fast = 0;
+        for (int it = 0; it < l.n_it; ++it) l.n_fast += tile2_side(it, ti, p->nvx) != 0 ? 1 : 0;
+        l.n_generic = l.n_it - l.n_fast;
         l.lds_sweep = sweep2_lds(ti, l.block, kc, l.elem);
         l.lds_moments = (size_t)kc * (l.block / 64) * 8 + (size_t)(l.block / 64) * 4 * 8;
         if (l.lds_sweep > kLdsBudget) return bad("tile needs more LDS than a workgroup has; lower tile_planes");

@@ -91,6 +91,25 @@ __host__ __device__ inline bool tile_is_special(int it, int ti, int nvx)
     if ((ti != 4 && ti != 8) || tile_is_fast(it, ti, nvx)) return false;
     return (it + 1) * ti <= nvx || tile_split(it, ti, nvx) == 0;
 }
+// Second-order tiles with a compiled fast body: every row of the tile and its
+// two halo rows on each side lies inside the v_x grid and off its first and
+// last cell, and all of them move the same way in x (v_x > 0 for all, or
+// v_x <= 0 for all).  Returns +1 (v_x > 0), -1 (v_x <= 0) or 0 (other).
+__host__ __device__ inline int tile2_side(int it, int ti, int nvx)
+{
+    const int lo = it * ti - 2, hi = it * ti + ti + 1;   // rows i0 - 2 .. i0 + ti + 1
+    if (lo < 1 || hi > nvx - 2) return 0;
+    if (2 * lo + 1 > nvx) return 1;
+    if (2 * hi + 1 <= nvx) return -1;
+    return 0;
+}
+
+// Whether tile `it` goes to the main sweep launch of its scheme.
+__host__ __device__ inline bool tile_main(int it, int ti, int nvx, int scheme)
+{
+    return scheme == FK_SCHEME_LIMITED2 ? tile2_side(it, ti, nvx) != 0 : tile_is_fast(it, ti, nvx);
+}
+
 int set_error(std::string* slot, int code, const std::string& msg);
 // error of the calling thread's last failed call that has no object, from a
 // message with static storage (no allocation)

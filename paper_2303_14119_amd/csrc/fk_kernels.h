@@ -520,315 +520,4 @@ __device__ __forceinline__ void moments_tile(const SweepArgs<T>& a, int wg, doub
     }
 }
 
-// Plane sums over the v_x tiles, one thread per x plane (coalesced over
-// consecutive planes), tiles added in order: the same sums the field
-// workgroup forms itself when it is given no plane_sum.
-__device__ __forceinline__ void plane_sums(const double* __restrict__ part_n, int nx, int n_it,
-                                           double* __restrict__ plane_sum)
-{
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nx) return;
-    double s = 0.0;
-#pragma unroll 16
-    for (int u = 0; u < n_it; ++u) s += part_n[(size_t)u * nx + k];
-    plane_sum[k] = s;
-}
-
-// ---------------------------------------------------------------- field
-
-struct FieldArgs {
-    const double* __restrict__ plane_sum;   // [nx] plane sums already reduced over the tiles, or null
-    const double* __restrict__ part_n;      // [n_it][nx] plane sums of the v_x tiles
-    const double* __restrict__ part_wall;   // [n_it][2]  wall primary, wall secondary
-    const double* __restrict__ part_top;    // [n_it]     flux through x = L
-    const double* __restrict__ part_lv;     // [nwg]      velocity-box outflow
-    const double* __restrict__ part_abs;    // [n_it][2]  absorbed at the wall and at x = L by a reversed
-                                            //            second-order step (read when abs_from_sweep)
-    const double* __restrict__ consts;  // zsum, srcnorm, injected per step, Eq 15 prefactor
-    double* __restrict__ ne;
-    double* __restrict__ ex;
-    double* __restrict__ dxk;
-    double* __restrict__ nudt;      // [nx] out: nu_ee dt per plane (collision term)
-    double* __restrict__ nudt_n;    // [nx] out: nu_ee dt n_e per plane
-    DevState* __restrict__ st;
-    fk_state* __restrict__ ring;
-    int nx, n_it, nwg, advance;
-    uint32_t mask;
-    int emission_norm, trace_stride, trace_cap;
-    double dx, dv2, dt, dvx, ex_ext;
-    double nudt_per_n;              // dt nu_ee / n_e of Eq 4 (0: no collision term)
-    double r_refl;                  // elastic (specular) share of the wall reflection R_f
-    double r_inel;                  // inelastic share of R_f, re-emitted in the Eq 15 shape
-    int abs_from_sweep;             // 1: the step's x sweep transported f after the velocity sweeps
-                                    //    (reversed second-order step); its absorbed fluxes are in part_abs
-};
-
-// Reduction of the moment partials of the new f over the v_x tiles (fixed
-// order), the 1D field solve and the wall bookkeeping; one workgroup of
-// kFieldThreads threads.  Thread t owns a contiguous segment of x planes and
-// keeps their densities in registers.  sh holds 2 * kFieldThreads doubles.
-constexpr int kFieldSegMax = 8;
-
-// Plane sums of planes kb .. kb + SEG - 1 (tiles in order) into n[0 .. SEG).
-// Either read from the reduced plane sums or added here from the tile
-// partials, four tiles' loads in flight before their adds.
-template <int SEG>
-__device__ __forceinline__ void plane_densities(const FieldArgs& a, int kb, double (&n)[kFieldSegMax])
-{
-    const int klast = a.nx - 1;
-#pragma unroll
-    for (int q = 0; q < kFieldSegMax; ++q) n[q] = 0.0;
-    if (a.plane_sum) {
-#pragma unroll
-        for (int q = 0; q < SEG; ++q) n[q] = a.plane_sum[min(kb + q, klast)];
-        return;
-    }
-    constexpr int kChunk = 4;
-    for (int u0 = 0; u0 < a.n_it; u0 += kChunk) {
-        double v[kChunk][SEG];
-#pragma unroll
-        for (int c = 0; c < kChunk; ++c) {
-            const double* row = a.part_n + (size_t)min(u0 + c, a.n_it - 1) * a.nx;
-#pragma unroll
-            for (int q = 0; q < SEG; ++q) v[c][q] = row[min(kb + q, klast)];
-        }
-#pragma unroll
-        for (int c = 0; c < kChunk; ++c)
-            if (u0 + c < a.n_it) {
-#pragma unroll
-                for (int q = 0; q < SEG; ++q) n[q] += v[c][q];
-            }
-    }
-}
-
-__device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
-{
-    const int t = threadIdx.x;
-    const int T = blockDim.x;
-    const int lane = t & 63, wave = t >> 6, nw = T >> 6;
-    const int seg = (a.nx + T - 1) / T;
-    const int kb = min(t * seg, a.nx), ke = min(kb + seg, a.nx);
-    const DevState old = *a.st;     // issued early: needed after the scans
-    const double zsum = a.consts[0], inj_step = a.consts[2], emit_pref = a.consts[3];
-
-    // Every global load comes before the first global store: one counter
-    // tracks both, so a load waited for after a store waits for the store
-    // too.  Loads use clamped indices and stay unconditional (values past
-    // the thread's segment are dropped).
-    //
-    // electron density per plane: sum over the v_x tiles in tile order
-    double nloc[kFieldSegMax];
-    double local = 0.0;
-    const bool in_regs = seg <= kFieldSegMax;
-    if (in_regs) {
-        if (seg == 1) plane_densities<1>(a, kb, nloc);
-        else if (seg == 2) plane_densities<2>(a, kb, nloc);
-        else if (seg <= 4) plane_densities<4>(a, kb, nloc);
-        else plane_densities<kFieldSegMax>(a, kb, nloc);
-#pragma unroll
-        for (int q = 0; q < kFieldSegMax; ++q)
-            if (kb + q < ke) {
-                nloc[q] *= a.dv2;
-                local += nloc[q];
-            }
-    } else {
-        for (int k = kb; k < ke; ++k) {
-            double sk = 0.0;
-            if (a.plane_sum) sk = a.plane_sum[k];
-            else
-                for (int u = 0; u < a.n_it; ++u) sk += a.part_n[(size_t)u * a.nx + k];
-            a.ne[k] = sk * a.dv2;
-            local += sk * a.dv2;
-        }
-    }
-    // wall, top and velocity-box partials: strided per thread, then over the
-    // waves in order
-    double pe = 0.0, see = 0.0, top = 0.0, lv = 0.0, abw = 0.0, abt = 0.0;
-    for (int u = t; u < a.n_it; u += T) {
-        pe += a.part_wall[2 * u];
-        see += a.part_wall[2 * u + 1];
-        top += a.part_top[u];
-        if (a.abs_from_sweep) {
-            abw += a.part_abs[2 * u];
-            abt += a.part_abs[2 * u + 1];
-        }
-    }
-    if (a.advance)
-        for (int w = t; w < a.nwg; w += T) lv += a.part_lv[w];
-
-    // exclusive prefix of the segment sums over the workgroup: wave scans,
-    // then a scan of the wave totals
-    const double incl = wave_total(local);     // inclusive scan over the wave
-    double excl = __shfl_up(incl, 1, 64);
-    if (lane == 0) excl = 0.0;
-    double* wtot = sh;              // [nw]
-    double* red = sh + 64;          // [nw][6]
-    double* red2 = red + 6 * 16;    // [nw][2]
-    if (lane == 63) wtot[wave] = incl;
-    pe = wave_sum(pe);
-    see = wave_sum(see);
-    top = wave_sum(top);
-    lv = wave_sum(lv);
-    if (a.abs_from_sweep) {
-        abw = wave_sum(abw);
-        abt = wave_sum(abt);
-    }
-    if (lane == 0) {
-        red[wave * 6 + 0] = pe;
-        red[wave * 6 + 1] = see;
-        red[wave * 6 + 2] = top;
-        red[wave * 6 + 3] = lv;
-        red2[wave * 2 + 0] = abw;
-        red2[wave * 2 + 1] = abt;
-    }
-    __syncthreads();
-    double wave_below = 0.0, total = 0.0;
-    for (int w = 0; w < nw; ++w) {
-        if (w < wave) wave_below += wtot[w];
-        total += wtot[w];
-    }
-    const double below0 = wave_below + excl;
-
-    // electrons the step's x sweep absorbed at the wall and let out at x = L:
-    // the fluxes of f^n, or on a reversed second-order step those of the
-    // array after the velocity sweeps (summed over the waves in order)
-    double g_abs = old.g_pe, top_abs = old.g_top;
-    if (a.abs_from_sweep && (a.mask & FK_PHYS_X)) {
-        double w0 = 0.0, w1 = 0.0;
-        for (int w = 0; w < nw; ++w) {
-            w0 += red2[w * 2 + 0];
-            w1 += red2[w * 2 + 1];
-        }
-        g_abs = w0 * a.dv2;
-        top_abs = w1 * a.dv2;
-    }
-    double sig = old.sigma, sig_lo = old.sigma_lo;
-    if (a.advance) {
-        // Eq 18 with the fluxes of f^n, Neumaier-compensated across steps;
-        // reflected electrons of both shares leave the wall again
-        const double inc = kE * a.dt * (old.g_see + (a.r_refl + a.r_inel) * old.g_pe - g_abs);
-        const double s = sig + inc;
-        if (fabs(sig) >= fabs(inc)) sig_lo += (sig - s) + inc;
-        else sig_lo += (inc - s) + sig;
-        sig = s;
-    }
-    const double sigma_now = sig + sig_lo;
-
-    // E_x at the cell centres: sigma / 2 eps0 minus the electron charge below
-    double run = below0, cmax = 0.0, bmax = 0.0;
-    const double e_wall = sigma_now / (2.0 * kEps0), e_per_n = kE / kEps0 * a.dx;
-    const double d_per_e = (a.mask & FK_PHYS_VX) ? -kE / kMe * a.dt / a.dvx : 0.0;   // Courant number per V/m
-    auto field_at = [&](int k, double nk) {
-        double e = 0.0;
-        if (a.mask & FK_PHYS_SELF_FIELD)
-            e = (a.mask & FK_PHYS_NO_SPACE_CHARGE) ? e_wall : e_wall - e_per_n * (run + 0.5 * nk);
-        e += a.ex_ext;
-        a.ex[k] = e;
-        const double d = d_per_e * e;
-        a.dxk[k] = d;
-        cmax = fmax(cmax, fabs(d));
-        if (a.nudt_per_n != 0.0) {
-            // collision term of the next step (Eq 3-4): nu_ee is linear in n_e
-            const double b = a.nudt_per_n * nk;
-            a.nudt[k] = b;
-            a.nudt_n[k] = b * nk;
-            bmax = fmax(bmax, b);
-        }
-        run += nk;
-    };
-    if (in_regs) {
-#pragma unroll
-        for (int q = 0; q < kFieldSegMax; ++q)
-            if (kb + q < ke) {
-                a.ne[kb + q] = nloc[q];
-                field_at(kb + q, nloc[q]);
-            }
-    } else {
-        for (int k = kb; k < ke; ++k) field_at(k, a.ne[k]);
-    }
-    cmax = wave_max_nonneg(cmax);
-    bmax = wave_max_nonneg(bmax);
-    if (lane == 0) {
-        red[wave * 6 + 4] = cmax;
-        red[wave * 6 + 5] = bmax;
-    }
-    __syncthreads();
-    if (t == 0) {
-        pe = see = top = lv = cmax = bmax = 0.0;
-        for (int w = 0; w < nw; ++w) {
-            pe += red[w * 6 + 0];
-            see += red[w * 6 + 1];
-            top += red[w * 6 + 2];
-            lv += red[w * 6 + 3];
-            cmax = fmax(cmax, red[w * 6 + 4]);
-            bmax = fmax(bmax, red[w * 6 + 5]);
-        }
-    }
-
-    if (t == 0) {
-        const bool x_on = a.mask & FK_PHYS_X;
-        const bool see_on = x_on && (a.mask & FK_PHYS_SEE);
-        const double g_pe = x_on ? pe * a.dv2 : 0.0;
-        const double g_see = see_on ? see * a.dv2 * (1.0 - a.r_refl - a.r_inel) : 0.0;   // 1 - R_f induce SEE
-        const double g_top = x_on ? top * a.dv2 : 0.0;
-        // the emission shape carries the secondaries and the inelastically
-        // reflected electrons
-        const double g_shape = g_see + (x_on ? a.r_inel * g_pe : 0.0);
-        double gscale = 0.0;
-        if (x_on) {
-            if (a.emission_norm == FK_EMIT_DISCRETE) gscale = zsum > 0.0 ? g_shape / zsum : 0.0;
-            else gscale = g_shape * emit_pref;
-        }
-        const double emitted = gscale * zsum + (x_on ? a.r_refl * g_pe : 0.0);
-        const double n_total = total * a.dx;
-        const double loss_v = a.advance ? lv * a.dx * a.dv2 : 0.0;
-        double resid = 0.0;
-        if (a.advance) {
-            const double inj = (a.mask & FK_PHYS_SRC) ? inj_step : 0.0;
-            resid = (n_total - old.n_total) - (a.dt * (old.emitted - g_abs - top_abs) + inj - loss_v);
-        }
-        DevState ns = old;
-        ns.step = old.step + (a.advance ? 1 : 0);
-        ns.sigma = sig;
-        ns.sigma_lo = sig_lo;
-        ns.g_pe = g_pe;
-        ns.g_see = g_see;
-        ns.g_top = g_top;
-        ns.emitted = emitted;
-        ns.loss_v = loss_v;
-        ns.n_total = n_total;
-        ns.resid = resid;
-        ns.gscale = gscale;
-        ns.courant_vx_max = fmax(old.courant_vx_max, cmax);
-        if (cmax > 1.0 || bmax > 1.0) ns.flags |= kFlagCfl;
-        if (!isfinite(n_total) || !isfinite(g_pe) || !isfinite(g_see) || !isfinite(g_top) ||
-            !isfinite(sigma_now))
-            ns.flags |= kFlagNonfinite;
-        *a.st = ns;
-        // trace slot: 32-bit arithmetic while the step count fits
-        int64_t rec = -1;
-        if (ns.step >= 0 && ns.step <= 0xffffffffLL) {
-            const unsigned st32 = (unsigned)ns.step, q = st32 / (unsigned)a.trace_stride;
-            if (q * (unsigned)a.trace_stride == st32) rec = q % (unsigned)a.trace_cap;
-        } else if (ns.step % a.trace_stride == 0) {
-            rec = (ns.step / a.trace_stride) % a.trace_cap;
-        }
-        if (rec >= 0) {
-            fk_state r;
-            r.step = ns.step;
-            r.t = (double)ns.step * a.dt;
-            r.sigma = sig;
-            r.sigma_lo = sig_lo;
-            r.g_pe = g_pe;
-            r.g_see = g_see;
-            r.g_top = g_top;
-            r.emitted = emitted;
-            r.loss_v = loss_v;
-            r.n_total = n_total;
-            r.resid = resid;
-            a.ring[rec] = r;
-        }
-    }
-}
-
 }  // namespace fk

@@ -510,13 +510,350 @@ __device__ __forceinline__ void sweep2_reversed(const SweepArgs<T>& a, int it, i
     tile_partials(a, t, it, kci, j, B, wsum, red, lv, spe, ssee, stop, abw, abt, true);
 }
 
+// ------------------------------------------------------------ fast bodies
+// Tiles whose rows and halo rows lie inside the v_x grid, off its first and
+// last cell, and all move the same way in x (UP: v_x > 0; else v_x <= 0):
+// no per-row lane masks, edge tests or direction choices, and each row keeps
+// only the planes its upwind faces read.  Rows are addressed by one lane
+// offset and a scalar row offset.
+
+template <typename T, int TI, bool UP>
+__device__ __forceinline__ void sweep2_forward_fast(const SweepArgs<T>& a, int it, int kci, double* smem, int j,
+                                                    int B)
+{
+    constexpr int R = TI + 4;
+    const Tile2<T> t = tile2(a, it, kci, j, B, TI);
+    T* xb = reinterpret_cast<T*>(smem);                                  // [2][R][W]
+    double* wsum = reinterpret_cast<double*>(xb + 2 * R * t.W);          // [kc][nw]
+    double* red = wsum + a.kc * t.nw;                                    // [nw][6]
+    T* tab = reinterpret_cast<T*>(red + t.nw * 6) + t.wave * 2 * (a.kc + 4);
+    for (int m = j; m < 2 * R; m += B) {
+        xb[m * t.W] = T(0);
+        xb[m * t.W + 1] = T(0);
+        xb[m * t.W + t.W - 2] = T(0);
+        xb[m * t.W + t.W - 1] = T(0);
+    }
+    const int es = (int)sizeof(T);
+    const int vb = t.jok ? (t.i0 - 2) * t.rb + j * es : kIdleLaneOffset;   // row i0 - 2 of this lane
+    // Courant number and the face coefficient of each row: (1 - c)/2 for
+    // v_x > 0, -(1 + c)/2 for v_x <= 0
+    T c[R], hc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        c[r] = a.x_on ? T(cell_v(t.i0 - 2 + r, a.nvx, a.dvx) * a.dt_dx) : T(0);
+        hc[r] = UP ? T(0.5) * (T(1) - c[r]) : -(T(0.5) * (T(1) + c[r]));
+    }
+    auto load_plane = [&](int kk, T (&dst)[R]) {
+        const bool in = kk >= 0 && kk < a.nx;
+        const rsrc_t pr = make_rsrc(a.fin + (size_t)(in ? kk : 0) * t.plane, in ? t.pbytes : 0u);
+#pragma unroll
+        for (int r = 0; r < R; ++r) dst[r] = bload<T>(pr, vb, r * t.rb);
+    };
+    // window: UP rows read planes k-1, k, k+1 (prefetch k+2); the others
+    // k, k+1, k+2 (prefetch k+3).  q0, q1, q2 hold them in that order.
+    T q0[R], q1[R], q2[R], qn[R], fp[R];
+    if (UP) {
+        T qmm[R];
+        load_plane(t.k0 - 2, qmm);
+        load_plane(t.k0 - 1, q0);
+        load_plane(t.k0, q1);
+        load_plane(t.k0 + 1, q2);
+        const bool zm = t.k0 - 1 <= 0 || t.k0 - 1 >= a.nx - 1;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const T s = zm ? T(0) : minmod(q0[r] - qmm[r], q1[r] - q0[r]);
+            fp[r] = t.k0 == 0 ? (a.x_on ? ghost_value(a, t.i0 - 2 + r, j, t.jok) : T(0)) : q0[r] + hc[r] * s;
+        }
+    } else {
+        load_plane(t.k0 - 1, qn);
+        load_plane(t.k0, q0);
+        load_plane(t.k0 + 1, q1);
+        load_plane(t.k0 + 2, q2);
+        const bool z0 = t.k0 <= 0 || t.k0 >= a.nx - 1;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const T s = z0 ? T(0) : minmod(q0[r] - qn[r], q1[r] - q0[r]);
+            fp[r] = q0[r] + hc[r] * s;
+        }
+    }
+    for (int m = t.lane; m < t.k1 - t.k0; m += 64) {
+        tab[m] = T(a.dxk[t.k0 + m]);
+        tab[a.kc + 4 + m] = T(a.srck[t.k0 + m]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    double lv = 0.0, spe = 0.0, ssee = 0.0, stop = 0.0;
+    const T dy = T(a.dy);
+    const rsrc_t psrc = make_rsrc(a.fsrc, t.pbytes);
+    for (int k = t.k0; k < t.k1; ++k) {
+        const T d_k = tab[k - t.k0];
+        const T s_k = tab[a.kc + 4 + k - t.k0];
+        load_plane(UP ? k + 2 : k + 3, qn);   // the next iteration's newest plane
+
+        // x sweep on all R rows: the face right of plane k carries plane k's
+        // value (UP) or plane k + 1's (else), moved by the limited slope
+        const bool z = UP ? (k <= 0 || k >= a.nx - 1) : (k + 1 >= a.nx - 1);
+        T u[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const T s = z ? T(0) : minmod(q1[r] - q0[r], q2[r] - q1[r]);
+            const T f = q1[r] + hc[r] * s;
+            const T cur = UP ? q1[r] : q0[r];
+            u[r] = cur - c[r] * (f - fp[r]);
+            fp[r] = f;
+        }
+        // v_x sweep by a_x(x_k): interior rows, no box edge in the tile
+        T f2[TI];
+        {
+            T sl[R];
+#pragma unroll
+            for (int r = 1; r < R - 1; ++r) sl[r] = minmod(u[r] - u[r - 1], u[r + 1] - u[r]);
+            if (d_k > T(0)) {
+                const T h = T(0.5) * (T(1) - d_k);
+#pragma unroll
+                for (int o = 0; o < TI; ++o)
+                    f2[o] = u[o + 2] - d_k * ((u[o + 2] + h * sl[o + 2]) - (u[o + 1] + h * sl[o + 1]));
+            } else {
+                const T h = T(0.5) * (T(1) + d_k);
+#pragma unroll
+                for (int o = 0; o < TI; ++o)
+                    f2[o] = u[o + 2] - d_k * ((u[o + 3] - h * sl[o + 3]) - (u[o + 2] - h * sl[o + 2]));
+            }
+        }
+        // v_y sweep by a_y
+        T f3[TI];
+        lv += vy_update<T, TI>(f2, f3, xb + (k & 1) * R * t.W, t.W, j, a.nvy, dy, t.jok, 0, TI);
+        // band source (Eq 7)
+        if (s_k != T(0)) {
+#pragma unroll
+            for (int r = 0; r < TI; ++r) f3[r] += s_k * bload<T>(psrc, vb, (r + 2) * t.rb);
+        }
+        {
+            const rsrc_t po = make_rsrc(a.fout + (size_t)k * t.plane, t.pbytes);
+            if (a.store_nt) {
+#pragma unroll
+                for (int r = 0; r < TI; ++r) bstore<T, kCpStream>(f3[r], po, vb, (r + 2) * t.rb);
+            } else {
+#pragma unroll
+                for (int r = 0; r < TI; ++r) bstore<T>(f3[r], po, vb, (r + 2) * t.rb);
+            }
+        }
+        plane_moments<T, TI>(a, t, k, f3, j, wsum, spe, ssee, stop);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            q0[r] = q1[r];
+            q1[r] = q2[r];
+            q2[r] = qn[r];
+        }
+    }
+    tile_partials(a, t, it, kci, j, B, wsum, red, lv, spe, ssee, stop, 0.0, 0.0, false);
+}
+
+template <typename T, int TI, bool UP>
+__device__ __forceinline__ void sweep2_reversed_fast(const SweepArgs<T>& a, int it, int kci, double* smem, int j,
+                                                     int B)
+{
+    constexpr int R = TI + 4;
+    const Tile2<T> t = tile2(a, it, kci, j, B, TI);
+    T* xb = reinterpret_cast<T*>(smem);                                  // [2][R][W]
+    double* wsum = reinterpret_cast<double*>(xb + 2 * R * t.W);          // [kc][nw]
+    double* red = wsum + a.kc * t.nw;                                    // [nw][6]
+    T* tab = reinterpret_cast<T*>(red + t.nw * 6) + t.wave * 2 * (a.kc + 4);
+    for (int m = j; m < 2 * R; m += B) {
+        xb[m * t.W] = T(0);
+        xb[m * t.W + 1] = T(0);
+        xb[m * t.W + t.W - 2] = T(0);
+        xb[m * t.W + t.W - 1] = T(0);
+    }
+    const int es = (int)sizeof(T);
+    const int vb = t.jok ? (t.i0 - 2) * t.rb + j * es : kIdleLaneOffset;
+    T c[TI], hc[TI];
+#pragma unroll
+    for (int o = 0; o < TI; ++o) {
+        c[o] = a.x_on ? T(cell_v(t.i0 + o, a.nvx, a.dvx) * a.dt_dx) : T(0);
+        hc[o] = UP ? T(0.5) * (T(1) - c[o]) : -(T(0.5) * (T(1) + c[o]));
+    }
+    for (int m = t.lane; m < t.k1 - t.k0 + 4; m += 64) {
+        const int kk = t.k0 - 2 + m;
+        const bool in = kk >= 0 && kk < a.nx;
+        tab[m] = in ? T(a.dxk[kk]) : T(0);
+        tab[a.kc + 4 + m] = in ? T(a.srck[kk]) : T(0);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    auto load_plane = [&](int kk, T (&dst)[R]) {
+        const bool in = kk >= 0 && kk < a.nx;
+        const rsrc_t pr = make_rsrc(a.fin + (size_t)(in ? kk : 0) * t.plane, in ? t.pbytes : 0u);
+#pragma unroll
+        for (int r = 0; r < R; ++r) dst[r] = bload<T>(pr, vb, r * t.rb);
+    };
+    const rsrc_t psrc = make_rsrc(a.fsrc, t.pbytes);
+    const T dy = T(a.dy);
+    double lv = 0.0, abw = 0.0, abt = 0.0;
+    // the velocity part of plane p (source, v_y, v_x); interior rows, so no
+    // box edge in v_x; the chunk's own planes tally the v_y loss and the
+    // absorbed fluxes
+    auto velocity = [&](int p, const T (&raw)[R], T (&h)[TI]) {
+        const T d_p = tab[p - t.k0 + 2];
+        const T s_p = tab[a.kc + 4 + p - t.k0 + 2];
+        T g[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) g[r] = raw[r];
+        if (s_p != T(0)) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) g[r] += s_p * bload<T>(psrc, vb, r * t.rb);
+        }
+        T y[R];
+        const double lvy = vy_update<T, R>(g, y, xb + (p & 1) * R * t.W, t.W, j, a.nvy, dy, t.jok, 2, TI + 2);
+        T sl[R];
+#pragma unroll
+        for (int r = 1; r < R - 1; ++r) sl[r] = minmod(y[r] - y[r - 1], y[r + 1] - y[r]);
+        if (d_p > T(0)) {
+            const T hh = T(0.5) * (T(1) - d_p);
+#pragma unroll
+            for (int o = 0; o < TI; ++o)
+                h[o] = y[o + 2] - d_p * ((y[o + 2] + hh * sl[o + 2]) - (y[o + 1] + hh * sl[o + 1]));
+        } else {
+            const T hh = T(0.5) * (T(1) + d_p);
+#pragma unroll
+            for (int o = 0; o < TI; ++o)
+                h[o] = y[o + 2] - d_p * ((y[o + 3] - hh * sl[o + 3]) - (y[o + 2] - hh * sl[o + 2]));
+        }
+        if (p >= t.k0 && p < t.k1) {
+            lv += lvy;
+            if (!UP && p == 0 && t.jok) {
+#pragma unroll
+                for (int o = 0; o < TI; ++o)
+                    if (2 * (t.i0 + o) + 1 < a.nvx) abw += -cell_v(t.i0 + o, a.nvx, a.dvx) * (double)h[o];
+            }
+            if (UP && p == a.nx - 1 && t.jok) {
+#pragma unroll
+                for (int o = 0; o < TI; ++o) abt += cell_v(t.i0 + o, a.nvx, a.dvx) * (double)h[o];
+            }
+        }
+    };
+
+    // the x window after the velocity part: UP rows read planes k-1, k, k+1
+    // (the velocity part runs one plane ahead), the others k, k+1, k+2 (two
+    // ahead); g0, g1, g2 hold them in that order
+    constexpr int AHEAD = UP ? 1 : 2;
+    T g0[TI], g1[TI], g2[TI], fp[TI];
+    T raw[R], rawn[R];
+    if (UP) {
+        T gm[TI];
+        load_plane(t.k0 - 2, raw);
+        load_plane(t.k0 - 1, rawn);
+        velocity(t.k0 - 2, raw, gm);
+        load_plane(t.k0, raw);
+        velocity(t.k0 - 1, rawn, g0);
+        load_plane(t.k0 + 1, rawn);
+        velocity(t.k0, raw, g1);
+        const bool zm = t.k0 - 1 <= 0 || t.k0 - 1 >= a.nx - 1;
+#pragma unroll
+        for (int o = 0; o < TI; ++o) {
+            const T s = zm ? T(0) : minmod(g0[o] - gm[o], g1[o] - g0[o]);
+            fp[o] = t.k0 == 0 ? (a.x_on ? ghost_value(a, t.i0 + o, j, t.jok) : T(0)) : g0[o] + hc[o] * s;
+        }
+        // rawn holds plane k0 + 1, the loop's first velocity plane
+#pragma unroll
+        for (int r = 0; r < R; ++r) raw[r] = rawn[r];
+    } else {
+        T gm[TI];
+        load_plane(t.k0 - 1, raw);
+        load_plane(t.k0, rawn);
+        velocity(t.k0 - 1, raw, gm);
+        load_plane(t.k0 + 1, raw);
+        velocity(t.k0, rawn, g0);
+        load_plane(t.k0 + 2, rawn);
+        velocity(t.k0 + 1, raw, g1);
+        const bool z0 = t.k0 <= 0 || t.k0 >= a.nx - 1;
+#pragma unroll
+        for (int o = 0; o < TI; ++o) {
+            const T s = z0 ? T(0) : minmod(g0[o] - gm[o], g1[o] - g0[o]);
+            fp[o] = g0[o] + hc[o] * s;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) raw[r] = rawn[r];   // plane k0 + 2
+    }
+
+    double spe = 0.0, ssee = 0.0, stop = 0.0;
+    for (int k = t.k0; k < t.k1; ++k) {
+        load_plane(k + AHEAD + 1, rawn);       // reads nothing useful near the end
+        velocity(k + AHEAD, raw, g2);
+        const bool z = UP ? (k <= 0 || k >= a.nx - 1) : (k + 1 >= a.nx - 1);
+        T out[TI];
+        if (UP) {
+            // window planes k-1 (g0), k (g1), k+1 (g2)
+#pragma unroll
+            for (int o = 0; o < TI; ++o) {
+                const T s = z ? T(0) : minmod(g1[o] - g0[o], g2[o] - g1[o]);
+                const T f = g1[o] + hc[o] * s;
+                out[o] = g1[o] - c[o] * (f - fp[o]);
+                fp[o] = f;
+            }
+        } else {
+            // window planes k (g0), k+1 (g1), k+2 (g2)
+#pragma unroll
+            for (int o = 0; o < TI; ++o) {
+                const T s = z ? T(0) : minmod(g1[o] - g0[o], g2[o] - g1[o]);
+                const T f = g1[o] + hc[o] * s;
+                out[o] = g0[o] - c[o] * (f - fp[o]);
+                fp[o] = f;
+            }
+        }
+        {
+            const rsrc_t po = make_rsrc(a.fout + (size_t)k * t.plane, t.pbytes);
+            if (a.store_nt) {
+#pragma unroll
+                for (int o = 0; o < TI; ++o) bstore<T, kCpStream>(out[o], po, vb, (o + 2) * t.rb);
+            } else {
+#pragma unroll
+                for (int o = 0; o < TI; ++o) bstore<T>(out[o], po, vb, (o + 2) * t.rb);
+            }
+        }
+        plane_moments<T, TI>(a, t, k, out, j, wsum, spe, ssee, stop);
+#pragma unroll
+        for (int o = 0; o < TI; ++o) {
+            g0[o] = g1[o];
+            g1[o] = g2[o];
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) raw[r] = rawn[r];
+    }
+    tile_partials(a, t, it, kci, j, B, wsum, red, lv, spe, ssee, stop, abw, abt, true);
+}
+
+// Main launch: the tiles with a fast body (tile list entries first).
+template <typename T, int TI, int MAXB, bool REV>
+__global__ void __launch_bounds__(MAXB) k_sweep2_fast(SweepArgs<T> a)
+{
+    extern __shared__ double smem[];
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int it = a.tile_list[wg % a.n_list];
+    const int kci = wg / a.n_list;
+    const bool up = tile2_side(it, TI, a.nvx) > 0;
+    if (REV) {
+        if (up) sweep2_reversed_fast<T, TI, true>(a, it, kci, smem, threadIdx.x, blockDim.x);
+        else sweep2_reversed_fast<T, TI, false>(a, it, kci, smem, threadIdx.x, blockDim.x);
+    } else {
+        if (up) sweep2_forward_fast<T, TI, true>(a, it, kci, smem, threadIdx.x, blockDim.x);
+        else sweep2_forward_fast<T, TI, false>(a, it, kci, smem, threadIdx.x, blockDim.x);
+    }
+}
+
+// The other tiles (edge tiles, tiles whose rows straddle v_x = 0): the
+// generic bodies with per-row masks.
 template <typename T, int TI, int MAXB, bool REV>
 __global__ void __launch_bounds__(MAXB) k_sweep2(SweepArgs<T> a)
 {
     extern __shared__ double smem[];
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
-    const int it = wg % a.n_it;
-    const int kci = wg / a.n_it;
+    const int it = a.tile_list[wg % a.n_list];
+    const int kci = wg / a.n_list;
     if (REV) sweep2_reversed<T, TI>(a, it, kci, smem, threadIdx.x, blockDim.x);
     else sweep2_forward<T, TI>(a, it, kci, smem, threadIdx.x, blockDim.x);
 }

@@ -32,6 +32,11 @@ EPS0 = 8.8541878128e-12
 # lies just beyond -1 rather than far outside the box
 FEATURE_RANGES = np.array([(1e6, 10e6), (1.5, 3.5), (250.0, 600.0), (1.0, 5.0), (0.5e-3, 5e-3),
                            (1 / 1024, 1 / 256), (1 / 192, 1 / 64)])
+# How far past [-1, 1] an encoded input may lie before the prediction is not
+# trusted and the run cold-starts instead: 0.1 for the physical inputs (the
+# sweep's own box), 0.75 for the two cell sizes (a finer grid than the
+# sweep's lies just below -1: 4096 x 384 x 384 encodes to -1.5 on both).
+FEATURE_MARGIN = np.array([0.1, 0.1, 0.1, 0.1, 0.1, 0.75, 0.75])
 
 
 def features_raw(ey, delta_max, a_max_ev, t_se_ev, length, nx, nv):
@@ -187,6 +192,7 @@ class Surrogate:
         self.net = fk.MLP(DIMS, max_batch=batch, stream=stream)
         self.net.set_params(init_params(DIMS, seed))
         self.step = 0
+        self.x_lo = self.x_hi = None      # box of the training inputs (encoded)
 
     def fit(self, X, Y, epochs=200, lr=1e-3, weight_decay=1e-4, seed=0, Xval=None, Yval=None, log=None):
         torch = self.torch
@@ -194,6 +200,7 @@ class Surrogate:
         n = len(X)
         X = np.ascontiguousarray(X, dtype=np.float32)
         Y = np.ascontiguousarray(Y, dtype=np.float32)
+        self.x_lo, self.x_hi = X.min(axis=0).astype(np.float64), X.max(axis=0).astype(np.float64)
         hist = []
         m = self.batch
         self.net.take_loss()                   # start the device-side loss sum afresh
@@ -232,16 +239,63 @@ class Surrogate:
     def params(self):
         return self.net.params()
 
-    def load(self, flat):
+    def load(self, flat, x_lo=None, x_hi=None):
         self.net.set_params(flat)
+        self.x_lo, self.x_hi = x_lo, x_hi
+
+    def save(self, path):
+        """Weights and the training inputs' box, FP32 / FP64, no pickles."""
+        np.savez(path, params=self.params(), dims=np.array(DIMS), x_lo=self.x_lo, x_hi=self.x_hi)
+
+    @classmethod
+    def from_file(cls, path, stream=None):
+        d = np.load(path)           # plain arrays only (allow_pickle stays off)
+        if list(d["dims"]) != DIMS:
+            raise ValueError(f"{path}: network shape {list(d['dims'])} is not {DIMS}")
+        sur = cls(stream=stream)
+        sur.load(d["params"], d["x_lo"] if "x_lo" in d else None, d["x_hi"] if "x_hi" in d else None)
+        return sur
+
+
+FEATURE_NAMES = ("|E_y|", "delta_max", "A_max", "T_se", "L", "1/N_x", "1/N_v")
+
+
+def trust_inputs(cfg, lo=None, hi=None):
+    """None if every encoded input of the run lies within the training box
+    [lo, hi] (default [-1, 1]: the sweep's ranges) widened by its margin,
+    else the reason it does not."""
+    x = features([cfg])[0].astype(np.float64)
+    if not np.all(np.isfinite(x)):
+        return "non-finite input"
+    lo = -np.ones(len(x)) if lo is None else np.asarray(lo, dtype=np.float64)
+    hi = np.ones(len(x)) if hi is None else np.asarray(hi, dtype=np.float64)
+    bad = [f"{FEATURE_NAMES[m]} encodes to {x[m]:.3f} (box [{lo[m]:.3f}, {hi[m]:.3f}])" for m in range(len(x))
+           if x[m] < lo[m] - FEATURE_MARGIN[m] or x[m] > hi[m] + FEATURE_MARGIN[m]]
+    return ("outside the training box: " + "; ".join(bad)) if bad else None
 
 
 def warm_start(solver, cfg, surrogate):
-    """Initialise a run from the surrogate's prediction for its parameters."""
-    y = surrogate.predict(features([cfg]))[0]
-    profile, g_pe, g_see = decode(y, cfg["ey"])
-    solver.warm_start(profile, cfg["t_se_ev"], step=0)
-    return profile
+    """Initialise a run from the surrogate's prediction for its parameters,
+    or leave it at the plain cold start (f = 0, sigma = 0, the paper's
+    initial state) when the inputs lie outside the training box or the
+    prediction is not usable.  Returns (profile or None, reason or None)."""
+    why = trust_inputs(cfg, getattr(surrogate, "x_lo", None), getattr(surrogate, "x_hi", None))
+    if why is None:
+        y = surrogate.predict(features([cfg]))[0]
+        if not np.all(np.isfinite(y)):
+            why = "non-finite prediction"
+        else:
+            profile, g_pe, g_see = decode(y, cfg["ey"])
+            if not (np.all(np.isfinite(profile)) and np.isfinite(g_pe) and np.isfinite(g_see)):
+                why = "non-finite decoded prediction"
+            else:
+                try:
+                    solver.warm_start(profile, cfg["t_se_ev"], step=0)
+                    return profile, None
+                except fk.FlashkinError as e:
+                    why = f"warm start refused: {e}"
+    solver.write_state(None, 0.0, 0.0, 0)      # the cold start
+    return None, why
 
 
 def time_to_saturation(solver, window_s=50e-12, rtol=1e-3, t_max=5e-9, check_steps=500, log=None, log_every=20000):
@@ -316,14 +370,13 @@ def train_cli(args, stream):
            "heldout_gpe_rel_median": float(np.median(err[:, 1])),
            "heldout_gsee_rel_median": float(np.median(err[:, 2])),
            "mean_predictor_profile_rel_l2_median": float(np.median(base[:, 0]))}
-    np.savez(args.out, params=sur.params(), dims=np.array(DIMS))
+    sur.save(args.out)
     print(json.dumps(rep), flush=True)
 
 
 def warmcold_cli(args, stream):
     cfg = W.c4()
-    sur = Surrogate(stream=stream)
-    sur.load(np.load(args.params)["params"])
+    sur = Surrogate.from_file(args.params, stream=stream)
     res = {}
     profiles = {}
     for mode in ("cold", "warm"):
@@ -331,8 +384,10 @@ def warmcold_cli(args, stream):
                        trace_stride=trace_stride(fk.validate(fk.make_params(cfg))["dt"])) as s:
             if mode == "warm":
                 t0 = time.perf_counter()
-                warm_start(s, cfg, sur)
+                prof0, why = warm_start(s, cfg, sur)
                 setup = time.perf_counter() - t0
+                if why:
+                    print("warm start fell back to the cold start:", why, flush=True)
             else:
                 setup = 0.0
             sat, steps, wall = time_to_saturation(s, t_max=args.t_max, check_steps=args.check_steps,

@@ -39,7 +39,7 @@ def test_short_bench_prints_the_contract_line():
     torch = pytest.importorskip("torch")
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    r = subprocess.run([sys.executable, "bench.py", "--steps", "20", "--warmup", "4", "--pre-steps", "16", "--no-cpu"],
+    r = subprocess.run([sys.executable, "bench.py", "--steps", "20", "--warmup", "4", "--pre-steps", "16", "--no-cpu", "--no-tts"],
                        cwd=ROOT, capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr[-2000:]
     line = [l for l in r.stdout.splitlines() if l.startswith("{")][-1]

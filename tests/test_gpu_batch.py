@@ -111,8 +111,12 @@ def test_autotune_keeps_state_and_results(fk):
         assert chosen["tile_rows"] in (4, 8, 12, 16)
         assert np.array_equal(a.f(), before)
         st2 = a.state()
-        for q in ("step", "sigma", "sigma_lo", "g_pe", "n_total"):
+        for q in ("step", "sigma", "sigma_lo"):
             assert st2[q] == st[q], q
+        # the moments are formed again from the chosen tiling's partials:
+        # the same to rounding
+        for q in ("g_pe", "n_total"):
+            assert abs(st2[q] - st[q]) <= 1e-14 * abs(st[q]), q
         a.step(80)
         tuned = a.f()
     o = Oracle(cfg)

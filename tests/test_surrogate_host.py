@@ -78,3 +78,92 @@ def test_init_params_layout_and_scale():
     w1 = p[:5 * 64].reshape(64, 5)
     assert abs(w1.std() - 1 / math.sqrt(5)) < 0.1
     assert np.all(p[5 * 64:5 * 64 + 64] == 0)
+
+
+# ------------------------------------------------ cold-start fallback (no GPU)
+
+class _Solver:
+    """Records what the warm-start helper asks of a solver."""
+
+    def __init__(self, refuse=False):
+        self.calls = []
+        self.refuse = refuse
+
+    def warm_start(self, profile, t_ev, step=0):
+        if self.refuse:
+            from paper_2303_14119_amd import flashkin as fk
+            raise fk.FlashkinError(fk.E_INVALID, "refused")
+        self.calls.append(("warm", np.asarray(profile).copy()))
+
+    def write_state(self, f=None, sigma=0.0, sigma_lo=0.0, step=0):
+        self.calls.append(("cold", sigma, step))
+
+
+class _Net:
+    def __init__(self, y, lo=None, hi=None):
+        self.y, self.x_lo, self.x_hi = y, lo, hi
+
+    def predict(self, X):
+        return np.repeat(self.y[None, :], len(X), axis=0)
+
+
+def _inside():
+    return W.config(nx=512, nvx=128, nvy=128, length=1e-3, ey=-5e6, delta_max=2.5, a_max_ev=400.0, t_se_ev=2.0)
+
+
+def test_warm_start_uses_a_finite_prediction_inside_the_box():
+    pytest.importorskip("paper_2303_14119_amd.flashkin")
+    y = np.zeros(S.NPTS + 2, dtype=np.float32)
+    y[:S.NPTS] = np.linspace(1.0, 0.0, S.NPTS)
+    s = _Solver()
+    prof, why = S.warm_start(s, _inside(), _Net(y))
+    assert why is None and s.calls[0][0] == "warm"
+    assert prof[0] == pytest.approx(2 * EPS0 * 5e6, rel=1e-6)
+
+
+@pytest.mark.parametrize("kw,word", [(dict(ey=-20e6), "|E_y|"), (dict(delta_max=5.0), "delta_max"),
+                                     (dict(nx=16), "1/N_x")])
+def test_inputs_outside_the_box_cold_start(kw, word):
+    pytest.importorskip("paper_2303_14119_amd.flashkin")
+    s = _Solver()
+    prof, why = S.warm_start(s, dict(_inside(), **kw), _Net(np.zeros(S.NPTS + 2, np.float32)))
+    assert prof is None and word in why and "outside the training box" in why
+    assert s.calls == [("cold", 0.0, 0)]
+
+
+def test_the_largest_run_is_inside_the_widened_box():
+    """4096 x 384 x 384 encodes its cell sizes to -1.5: within the grid
+    inputs' margin of the sweep's box."""
+    assert S.trust_inputs(W.c4()) is None
+    assert "1/N_x" in S.trust_inputs(dict(W.c4(), nx=8))
+
+
+def test_non_finite_prediction_cold_starts():
+    pytest.importorskip("paper_2303_14119_amd.flashkin")
+    y = np.zeros(S.NPTS + 2, dtype=np.float32)
+    y[7] = np.nan
+    s = _Solver()
+    prof, why = S.warm_start(s, _inside(), _Net(y))
+    assert prof is None and why == "non-finite prediction" and s.calls == [("cold", 0.0, 0)]
+    y = np.zeros(S.NPTS + 2, dtype=np.float32)
+    y[S.NPTS] = 1e30                       # decodes to an infinite flux
+    s = _Solver()
+    prof, why = S.warm_start(s, _inside(), _Net(y))
+    assert prof is None and "non-finite" in why
+
+
+def test_refused_warm_start_cold_starts():
+    pytest.importorskip("paper_2303_14119_amd.flashkin")
+    s = _Solver(refuse=True)
+    prof, why = S.warm_start(s, _inside(), _Net(np.zeros(S.NPTS + 2, np.float32)))
+    assert prof is None and why.startswith("warm start refused") and s.calls == [("cold", 0.0, 0)]
+
+
+def test_training_box_narrows_the_trust():
+    """A network that only saw a part of the box trusts only that part (plus
+    the margins)."""
+    lo = -np.ones(7)
+    hi = np.ones(7)
+    hi[0] = -0.5                           # trained on |E_y| up to 3.25 MV/m
+    assert S.trust_inputs(_inside(), lo, hi) is not None
+    assert S.trust_inputs(dict(_inside(), ey=-3.3e6), lo, hi) is None
