@@ -124,7 +124,9 @@ def time_to_saturation(cfg, stream, t_max=5e-9):
                 t0 = time.perf_counter()
                 _, why = S.warm_start(s, cfg, sur)
                 setup = time.perf_counter() - t0
-            sat, steps, wall = S.time_to_saturation(s, t_max=t_max, check_steps=500)
+            sat, steps, wall = S.time_to_saturation(
+                s, t_max=t_max, check_steps=500,
+                log=lambda m, mode=mode: print(f"time to saturation, {mode} start:{m}", file=sys.stderr, flush=True))
             st = s.state()
             profiles[mode] = s.profile(S.NPTS)
         out[mode] = {"saturated": bool(sat), "steps": steps, "sim_time_s": steps * dt, "wall_s": round(wall, 3),

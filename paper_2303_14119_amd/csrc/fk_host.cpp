@@ -46,7 +46,7 @@ size_t sweep2_lds(int ti, int block, int kc, int elem)
 {
     const int waves = (block + 63) / 64;
     return (size_t)2 * (ti + 4) * (block + 4) * elem + (size_t)kc * waves * 8 + (size_t)waves * 6 * 8 +
-           (size_t)waves * 2 * (kc + 4) * elem;
+           (size_t)waves * 2 * (kc + 4) * elem + (size_t)waves * 256 * elem;
 }
 
 int derive_layout(const fk_params* p, Layout* L, std::string* why)
@@ -126,8 +126,8 @@ int derive_layout(const fk_params* p, Layout* L, std::string* why)
         }
         if (ti != 4 && ti != 8) return bad("FK_SCHEME_LIMITED2 takes tile_rows 4 or 8");
         if (sweep2_lds(ti, l.block, 4, l.elem) > kLdsBudget)
-            return bad("FK_SCHEME_LIMITED2: the v_y exchange does not fit in LDS (nvy up to 960 in FP32 with 4-row tiles, "
-                       "512 with 8; 448 in FP64)");
+            return bad("FK_SCHEME_LIMITED2: the v_y exchange does not fit in LDS (nvy up to 768 in FP32 with 4-row tiles, "
+                       "512 with 8; 384 in FP64)");
         l.ti = ti;
         l.n_it = (p->nvx + ti - 1) / ti;
         int kc = p->tile_planes;

@@ -35,11 +35,13 @@
 namespace fk {
 
 // minmod of two differences: the one nearer zero if they agree in sign,
-// else 0 (exact: only min, max and an addition of zero)
+// else 0.  In FP32 it is the median of (a, b, 0), one v_med3 instruction; in
+// FP64 min, max and an addition of zero.  Both are exact.
 template <typename T>
 __device__ __forceinline__ T minmod(T a, T b)
 {
-    return fmax(fmin(a, b), T(0)) + fmin(fmax(a, b), T(0));
+    if constexpr (sizeof(T) == 4) return __builtin_amdgcn_fmed3f(a, b, 0.0f);
+    else return fmax(fmin(a, b), T(0)) + fmin(fmax(a, b), T(0));
 }
 
 // The limited 1D update along a line of values held by one thread (v_x
@@ -82,7 +84,9 @@ __device__ __forceinline__ double vx_update(const T (&u)[R], const bool (&edge)[
 // The limited v_y update of NR rows held one column per thread: values go
 // through LDS (buf: NR rows of W = B + 4 columns, the lane at column j + 2),
 // one barrier.  Returns the box loss of this lane over rows [own_lo, own_hi)
-// (the tile's own rows; halo rows are tallied by their own tile).
+// (the tile's own rows; halo rows are tallied by their own tile).  jok false
+// zeroes the output (callers whose idle lanes never reach memory or the sums
+// pass true).
 template <typename T, int NR>
 __device__ __forceinline__ double vy_update(const T (&v)[NR], T (&out)[NR], T* buf, int W, int j, int nvy, T dy,
                                             bool jok, int own_lo, int own_hi)
@@ -90,32 +94,45 @@ __device__ __forceinline__ double vy_update(const T (&v)[NR], T (&out)[NR], T* b
 #pragma unroll
     for (int r = 0; r < NR; ++r) buf[r * W + j + 2] = v[r];
     __syncthreads();
-    const bool em = j - 1 <= 0 || j - 1 >= nvy - 1;   // slope of column j - 1 is zero
-    const bool e0 = j <= 0 || j >= nvy - 1;
-    const bool ep = j + 1 >= nvy - 1;
-    double lv = 0.0;
+    // With s(m) the minmod slope of column m and h the face coefficient:
+    // dy > 0: res = b0 - dy (b0 - a1) - dy h s(j) + dy h s(j - 1);
+    // dy < 0: res = b0 - dy (c1 - b0) + dy h s(j + 1) - dy h s(j).
+    // Slopes are zero in the first and last column and outside the grid;
+    // those factors are folded into the per-lane coefficients e0, em, ep.
+    const T fm = (j - 1 <= 0 || j - 1 >= nvy - 1) ? T(0) : T(1);
+    const T f0 = (j <= 0 || j >= nvy - 1) ? T(0) : T(1);
+    const T fpl = (j + 1 >= nvy - 1) ? T(0) : T(1);
+    const T h = dy > T(0) ? T(0.5) * (T(1) - dy) : T(0.5) * (T(1) + dy);
+    const T e0 = dy * h * f0;
+    T lvr = T(0);   // the lane's outflow over its own rows (only the edge lanes use it)
+    // one uniform branch on the sign of dy, outside the row loop
+    if (dy > T(0)) {
+        const T em = dy * h * fm;
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const T* row = buf + r * W + j + 2;
-        const T a2 = row[-2], a1 = row[-1], b0 = v[r], c1 = row[1], c2 = row[2];
-        const T s0 = e0 ? T(0) : minmod(b0 - a1, c1 - b0);
-        T res;
-        if (dy > T(0)) {
-            const T h = T(0.5) * (T(1) - dy);
-            const T sm = em ? T(0) : minmod(a1 - a2, b0 - a1);
-            res = b0 - dy * ((b0 + h * s0) - (a1 + h * sm));
-        } else {
-            const T h = T(0.5) * (T(1) + dy);
-            const T sp = ep ? T(0) : minmod(c1 - b0, c2 - c1);
-            res = b0 - dy * ((c1 - h * sp) - (b0 - h * s0));
+        for (int r = 0; r < NR; ++r) {
+            const T* row = buf + r * W + j + 2;
+            const T a2 = row[-2], a1 = row[-1], b0 = v[r], c1 = row[1];
+            const T d = b0 - a1;
+            const T res = fma(em, minmod(a1 - a2, d), fma(-e0, minmod(d, c1 - b0), fma(-dy, d, b0)));
+            out[r] = jok ? res : T(0);
+            if (r >= own_lo && r < own_hi) lvr += b0;
         }
-        out[r] = jok ? res : T(0);
-        if (r >= own_lo && r < own_hi) {
-            if (dy > T(0) && j == nvy - 1) lv += (double)dy * (double)b0;
-            if (dy < T(0) && j == 0) lv -= (double)dy * (double)b0;
+    } else {
+        const T ep = dy * h * fpl;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const T* row = buf + r * W + j + 2;
+            const T a1 = row[-1], b0 = v[r], c1 = row[1], c2 = row[2];
+            const T d = c1 - b0;
+            const T res = fma(-e0, minmod(b0 - a1, d), fma(ep, minmod(d, c2 - c1), fma(-dy, d, b0)));
+            out[r] = jok ? res : T(0);
+            if (r >= own_lo && r < own_hi) lvr += b0;
         }
     }
-    return lv;
+    // what leaves through +v_max (dy > 0, last column) or -v_max (dy < 0,
+    // first column): dy times the edge cell (its slope is zero)
+    if ((dy > T(0) && j == nvy - 1) || (dy < T(0) && j == 0)) return fabs((double)dy) * (double)lvr;
+    return 0.0;
 }
 
 // The x update of one output plane k for the rows of a tile (one value per
@@ -204,17 +221,44 @@ __device__ __forceinline__ T ghost_value(const SweepArgs<T>& a, int i, int j, bo
     return T(g);
 }
 
-// Moments of the output plane k (plane sum through LDS slots, wall partials
-// at k = 0, top partial at k = nx - 1) for output rows out[0 .. TI).
+// Plane sums of a batch of up to four planes of one wave: lane 16p + q adds
+// the row sums of lanes 4q .. 4q + 3 of batch plane p in FP64, a shift-and-
+// add inside each row of 16 lanes (by 1, 2, 4, 8) leaves the plane's total
+// in lane 16p + 15, which writes it to the block's slot.  kb: the batch's
+// first plane, relative to k0; last: the last plane written.
+template <typename T>
+__device__ __forceinline__ void flush_plane_sums(const Tile2<T>& t, const T* ring, int kb, int last, double* wsum)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int p = t.lane >> 4, q = t.lane & 15;
+    const T* src = ring + p * 64 + q * 4;
+    double v = ((double)src[0] + (double)src[1]) + ((double)src[2] + (double)src[3]);
+    v += dpp_move<0x111, 0xf>(v);   // row_shr:1
+    v += dpp_move<0x112, 0xf>(v);   // row_shr:2
+    v += dpp_move<0x114, 0xf>(v);   // row_shr:4
+    v += dpp_move<0x118, 0xf>(v);   // row_shr:8
+    if (q == 15 && kb + p <= last) wsum[(kb + p) * t.nw + t.wave] = v;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Moments of the output plane k for output rows out[0 .. TI): the lane's
+// row sum (in T: four or eight values) into the wave's ring of four planes,
+// the plane sums every fourth plane and at the chunk's end; wall partials at
+// k = 0, top partial at k = nx - 1.
 template <typename T, int TI>
 __device__ __forceinline__ void plane_moments(const SweepArgs<T>& a, const Tile2<T>& t, int k, const T (&out)[TI],
-                                              int j, double* wsum, double& spe, double& ssee, double& stop)
+                                              int j, T* ring, double* wsum, double& spe, double& ssee, double& stop)
 {
-    double sn = 0.0;
+    T rs = T(0);
 #pragma unroll
-    for (int r = 0; r < TI; ++r) sn += (double)out[r];
-    sn = wave_total(t.jok ? sn : 0.0);
-    if (t.lane == 63) wsum[(k - t.k0) * t.nw + t.wave] = sn;
+    for (int r = 0; r < TI; ++r) rs += out[r];
+    const int kr = k - t.k0;
+    ring[(kr & 3) * 64 + t.lane] = t.jok ? rs : T(0);
+    if ((kr & 3) == 3 || k == t.k1 - 1) flush_plane_sums(t, ring, kr & ~3, kr, wsum);
     if (k == 0 && t.jok) {
 #pragma unroll
         for (int r = 0; r < TI; ++r) {
@@ -293,6 +337,7 @@ __device__ __forceinline__ void sweep2_forward(const SweepArgs<T>& a, int it, in
     double* wsum = reinterpret_cast<double*>(xb + 2 * R * t.W);          // [kc][nw]
     double* red = wsum + a.kc * t.nw;                                    // [nw][6]
     T* tab = reinterpret_cast<T*>(red + t.nw * 6) + t.wave * 2 * (a.kc + 4);
+    T* ring = reinterpret_cast<T*>(red + t.nw * 6) + t.nw * 2 * (a.kc + 4) + t.wave * 256;   // [4][64]
     for (int m = j; m < 2 * R; m += B) {
         xb[m * t.W] = T(0);
         xb[m * t.W + 1] = T(0);
@@ -367,7 +412,7 @@ __device__ __forceinline__ void sweep2_forward(const SweepArgs<T>& a, int it, in
 #pragma unroll
             for (int r = 0; r < TI; ++r) bstore<T>(f3[r], po, vo[r + 2], 0);
         }
-        plane_moments<T, TI>(a, t, k, f3, j, wsum, spe, ssee, stop);
+        plane_moments<T, TI>(a, t, k, f3, j, ring, wsum, spe, ssee, stop);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             wm[r] = w0[r];
@@ -390,6 +435,7 @@ __device__ __forceinline__ void sweep2_reversed(const SweepArgs<T>& a, int it, i
     double* wsum = reinterpret_cast<double*>(xb + 2 * R * t.W);          // [kc][nw]
     double* red = wsum + a.kc * t.nw;                                    // [nw][6]
     T* tab = reinterpret_cast<T*>(red + t.nw * 6) + t.wave * 2 * (a.kc + 4);
+    T* ring = reinterpret_cast<T*>(red + t.nw * 6) + t.nw * 2 * (a.kc + 4) + t.wave * 256;   // [4][64]
     for (int m = j; m < 2 * R; m += B) {
         xb[m * t.W] = T(0);
         xb[m * t.W + 1] = T(0);
@@ -497,7 +543,7 @@ __device__ __forceinline__ void sweep2_reversed(const SweepArgs<T>& a, int it, i
 #pragma unroll
             for (int o = 0; o < TI; ++o) bstore<T>(out[o], po, vo[o + 2], 0);
         }
-        plane_moments<T, TI>(a, t, k, out, j, wsum, spe, ssee, stop);
+        plane_moments<T, TI>(a, t, k, out, j, ring, wsum, spe, ssee, stop);
 #pragma unroll
         for (int o = 0; o < TI; ++o) {
             hm[o] = h0[o];
@@ -527,6 +573,7 @@ __device__ __forceinline__ void sweep2_forward_fast(const SweepArgs<T>& a, int i
     double* wsum = reinterpret_cast<double*>(xb + 2 * R * t.W);          // [kc][nw]
     double* red = wsum + a.kc * t.nw;                                    // [nw][6]
     T* tab = reinterpret_cast<T*>(red + t.nw * 6) + t.wave * 2 * (a.kc + 4);
+    T* ring = reinterpret_cast<T*>(red + t.nw * 6) + t.nw * 2 * (a.kc + 4) + t.wave * 256;   // [4][64]
     for (int m = j; m < 2 * R; m += B) {
         xb[m * t.W] = T(0);
         xb[m * t.W + 1] = T(0);
@@ -594,15 +641,24 @@ __device__ __forceinline__ void sweep2_forward_fast(const SweepArgs<T>& a, int i
 
         // x sweep on all R rows: the face right of plane k carries plane k's
         // value (UP) or plane k + 1's (else), moved by the limited slope
+        // (one uniform branch: the slope is zero in the first and last plane)
         const bool z = UP ? (k <= 0 || k >= a.nx - 1) : (k + 1 >= a.nx - 1);
         T u[R];
+        if (z) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const T s = z ? T(0) : minmod(q1[r] - q0[r], q2[r] - q1[r]);
-            const T f = q1[r] + hc[r] * s;
-            const T cur = UP ? q1[r] : q0[r];
-            u[r] = cur - c[r] * (f - fp[r]);
-            fp[r] = f;
+            for (int r = 0; r < R; ++r) {
+                const T cur = UP ? q1[r] : q0[r];
+                u[r] = cur - c[r] * (q1[r] - fp[r]);
+                fp[r] = q1[r];
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const T f = q1[r] + hc[r] * minmod(q1[r] - q0[r], q2[r] - q1[r]);
+                const T cur = UP ? q1[r] : q0[r];
+                u[r] = cur - c[r] * (f - fp[r]);
+                fp[r] = f;
+            }
         }
         // v_x sweep by a_x(x_k): interior rows, no box edge in the tile
         T f2[TI];
@@ -624,7 +680,7 @@ __device__ __forceinline__ void sweep2_forward_fast(const SweepArgs<T>& a, int i
         }
         // v_y sweep by a_y
         T f3[TI];
-        lv += vy_update<T, TI>(f2, f3, xb + (k & 1) * R * t.W, t.W, j, a.nvy, dy, t.jok, 0, TI);
+        lv += vy_update<T, TI>(f2, f3, xb + (k & 1) * R * t.W, t.W, j, a.nvy, dy, true, 0, TI);
         // band source (Eq 7)
         if (s_k != T(0)) {
 #pragma unroll
@@ -640,7 +696,7 @@ __device__ __forceinline__ void sweep2_forward_fast(const SweepArgs<T>& a, int i
                 for (int r = 0; r < TI; ++r) bstore<T>(f3[r], po, vb, (r + 2) * t.rb);
             }
         }
-        plane_moments<T, TI>(a, t, k, f3, j, wsum, spe, ssee, stop);
+        plane_moments<T, TI>(a, t, k, f3, j, ring, wsum, spe, ssee, stop);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             q0[r] = q1[r];
@@ -661,6 +717,7 @@ __device__ __forceinline__ void sweep2_reversed_fast(const SweepArgs<T>& a, int 
     double* wsum = reinterpret_cast<double*>(xb + 2 * R * t.W);          // [kc][nw]
     double* red = wsum + a.kc * t.nw;                                    // [nw][6]
     T* tab = reinterpret_cast<T*>(red + t.nw * 6) + t.wave * 2 * (a.kc + 4);
+    T* ring = reinterpret_cast<T*>(red + t.nw * 6) + t.nw * 2 * (a.kc + 4) + t.wave * 256;   // [4][64]
     for (int m = j; m < 2 * R; m += B) {
         xb[m * t.W] = T(0);
         xb[m * t.W + 1] = T(0);
@@ -708,7 +765,7 @@ __device__ __forceinline__ void sweep2_reversed_fast(const SweepArgs<T>& a, int 
             for (int r = 0; r < R; ++r) g[r] += s_p * bload<T>(psrc, vb, r * t.rb);
         }
         T y[R];
-        const double lvy = vy_update<T, R>(g, y, xb + (p & 1) * R * t.W, t.W, j, a.nvy, dy, t.jok, 2, TI + 2);
+        const double lvy = vy_update<T, R>(g, y, xb + (p & 1) * R * t.W, t.W, j, a.nvy, dy, true, 2, TI + 2);
         T sl[R];
 #pragma unroll
         for (int r = 1; r < R - 1; ++r) sl[r] = minmod(y[r] - y[r - 1], y[r + 1] - y[r]);
@@ -784,24 +841,21 @@ __device__ __forceinline__ void sweep2_reversed_fast(const SweepArgs<T>& a, int 
     for (int k = t.k0; k < t.k1; ++k) {
         load_plane(k + AHEAD + 1, rawn);       // reads nothing useful near the end
         velocity(k + AHEAD, raw, g2);
+        // UP: window planes k-1 (g0), k (g1), k+1 (g2); else k, k+1, k+2.
+        // One uniform branch: the slope is zero in the first and last plane.
         const bool z = UP ? (k <= 0 || k >= a.nx - 1) : (k + 1 >= a.nx - 1);
         T out[TI];
-        if (UP) {
-            // window planes k-1 (g0), k (g1), k+1 (g2)
+        if (z) {
 #pragma unroll
             for (int o = 0; o < TI; ++o) {
-                const T s = z ? T(0) : minmod(g1[o] - g0[o], g2[o] - g1[o]);
-                const T f = g1[o] + hc[o] * s;
-                out[o] = g1[o] - c[o] * (f - fp[o]);
-                fp[o] = f;
+                out[o] = (UP ? g1[o] : g0[o]) - c[o] * (g1[o] - fp[o]);
+                fp[o] = g1[o];
             }
         } else {
-            // window planes k (g0), k+1 (g1), k+2 (g2)
 #pragma unroll
             for (int o = 0; o < TI; ++o) {
-                const T s = z ? T(0) : minmod(g1[o] - g0[o], g2[o] - g1[o]);
-                const T f = g1[o] + hc[o] * s;
-                out[o] = g0[o] - c[o] * (f - fp[o]);
+                const T f = g1[o] + hc[o] * minmod(g1[o] - g0[o], g2[o] - g1[o]);
+                out[o] = (UP ? g1[o] : g0[o]) - c[o] * (f - fp[o]);
                 fp[o] = f;
             }
         }
@@ -815,7 +869,7 @@ __device__ __forceinline__ void sweep2_reversed_fast(const SweepArgs<T>& a, int 
                 for (int o = 0; o < TI; ++o) bstore<T>(out[o], po, vb, (o + 2) * t.rb);
             }
         }
-        plane_moments<T, TI>(a, t, k, out, j, wsum, spe, ssee, stop);
+        plane_moments<T, TI>(a, t, k, out, j, ring, wsum, spe, ssee, stop);
 #pragma unroll
         for (int o = 0; o < TI; ++o) {
             g0[o] = g1[o];
@@ -828,8 +882,16 @@ __device__ __forceinline__ void sweep2_reversed_fast(const SweepArgs<T>& a, int 
 }
 
 // Main launch: the tiles with a fast body (tile list entries first).
+// Waves per SIMD the fast bodies are compiled for (FP32: 4-row tiles 4,
+// 8-row tiles 3; FP64: 2), which caps their registers at 512 / waves.
+template <typename T, int TI>
+constexpr int sweep2_waves()
+{
+    return sizeof(T) == 4 ? (TI <= 4 ? 4 : 3) : 2;
+}
+
 template <typename T, int TI, int MAXB, bool REV>
-__global__ void __launch_bounds__(MAXB) k_sweep2_fast(SweepArgs<T> a)
+__global__ void __launch_bounds__(MAXB, (sweep2_waves<T, TI>())) k_sweep2_fast(SweepArgs<T> a)
 {
     extern __shared__ double smem[];
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
