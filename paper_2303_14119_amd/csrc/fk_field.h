@@ -182,21 +182,35 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
             cadd(ltot, cvalue(sk) * a.dv2);
         }
     }
-    // wall, top, velocity-box and absorbed partials: compensated sums,
-    // strided per thread, then over the lanes and the waves in order
+    // wall, top, velocity-box and absorbed partials: compensated sums.  The
+    // n_it tile partials go to wave 0 and the nwg box-loss partials to wave
+    // 1 (wave 0 in a one-wave workgroup), strided over the lanes; the other
+    // waves hold zeros, which leave a compensated sum unchanged.
     constexpr int kParts = 6;       // primary, secondary, top, box loss, absorbed at wall / top
+    const int lv_wave = nw > 1 ? 1 : 0;
     CSum part[kParts];
-    for (int u = t; u < a.n_it; u += T) {
-        cadd(part[0], a.part_wall[2 * u]);
-        cadd(part[1], a.part_wall[2 * u + 1]);
-        cadd(part[2], a.part_top[u]);
-        if (a.abs_from_sweep) {
-            cadd(part[4], a.part_abs[2 * u]);
-            cadd(part[5], a.part_abs[2 * u + 1]);
+    if (wave == 0) {
+        for (int u = lane; u < a.n_it; u += 64) {
+            cadd(part[0], a.part_wall[2 * u]);
+            cadd(part[1], a.part_wall[2 * u + 1]);
+            cadd(part[2], a.part_top[u]);
+            if (a.abs_from_sweep) {
+                cadd(part[4], a.part_abs[2 * u]);
+                cadd(part[5], a.part_abs[2 * u + 1]);
+            }
         }
     }
-    if (a.advance)
-        for (int w = t; w < a.nwg; w += T) cadd(part[3], a.part_lv[w]);
+    if (a.advance && wave == lv_wave) {
+        // eight loads in flight per lane before their adds
+        for (int w0 = lane; w0 < a.nwg; w0 += 64 * 8) {
+            double v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = a.part_lv[min(w0 + 64 * q, a.nwg - 1)];
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (w0 + 64 * q < a.nwg) cadd(part[3], v[q]);
+        }
+    }
 
     // exclusive prefix of the segment sums over the workgroup: wave scans,
     // then a scan of the wave totals
@@ -205,10 +219,19 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
     if (lane == 0) excl = 0.0;
     double* wtot = sh;              // [nw]
     double* red = sh + 64;          // [nw][kParts + 1][2]: (s, c) pairs of the partials and the electron total
+    double* tots = red + 16 * (kParts + 1) * 2 + 32;   // [kParts + 1] the totals over the waves
     if (lane == 63) wtot[wave] = incl;
     ltot = wave_csum(ltot);
-#pragma unroll
-    for (int m = 0; m < kParts; ++m) part[m] = wave_csum(part[m]);
+    if (wave == 0) {
+        part[0] = wave_csum(part[0]);
+        part[1] = wave_csum(part[1]);
+        part[2] = wave_csum(part[2]);
+        if (a.abs_from_sweep) {
+            part[4] = wave_csum(part[4]);
+            part[5] = wave_csum(part[5]);
+        }
+    }
+    if (wave == lv_wave) part[3] = wave_csum(part[3]);
     if (lane == 0) {
         double* r = red + wave * (kParts + 1) * 2;
 #pragma unroll
@@ -223,28 +246,32 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
     double wave_below = 0.0;
     for (int w = 0; w < wave; ++w) wave_below += wtot[w];
     const double below0 = wave_below + excl;
-    // the partials and the electron total over the waves, in order
-    CSum tot[kParts + 1];
-    for (int w = 0; w < nw; ++w) {
-        const double* r = red + w * (kParts + 1) * 2;
-#pragma unroll
-        for (int m = 0; m <= kParts; ++m) {
+    // the partials and the electron total over the waves, in order: thread m
+    // of wave 0 merges quantity m
+    if (t <= kParts) {
+        CSum acc;
+        for (int w = 0; w < nw; ++w) {
             CSum x;
-            x.s = r[2 * m];
-            x.c = r[2 * m + 1];
-            tot[m] = cmerge(tot[m], x);
+            x.s = red[w * (kParts + 1) * 2 + 2 * t];
+            x.c = red[w * (kParts + 1) * 2 + 2 * t + 1];
+            acc = cmerge(acc, x);
         }
+        tots[t] = cvalue(acc);
     }
-    const double pe = cvalue(tot[0]), see = cvalue(tot[1]), top = cvalue(tot[2]), lv = cvalue(tot[3]);
-    const double total = cvalue(tot[kParts]);
+    __syncthreads();
+    double tot[kParts + 1];
+#pragma unroll
+    for (int m = 0; m <= kParts; ++m) tot[m] = tots[m];
+    const double pe = tot[0], see = tot[1], top = tot[2], lv = tot[3];
+    const double total = tot[kParts];
 
     // electrons the step's x sweep absorbed at the wall and let out at x = L:
     // the fluxes of f^n, or on a reversed second-order step those of the
     // array after the velocity sweeps
     double g_abs = old.g_pe, top_abs = old.g_top;
     if (a.abs_from_sweep && (a.mask & FK_PHYS_X)) {
-        g_abs = cvalue(tot[4]) * a.dv2;
-        top_abs = cvalue(tot[5]) * a.dv2;
+        g_abs = tot[4] * a.dv2;
+        top_abs = tot[5] * a.dv2;
     }
     double sig = old.sigma, sig_lo = old.sigma_lo;
     if (a.advance) {
