@@ -175,8 +175,9 @@ def bench_batch(args):
 
 
 def bench_mlp(args):
-    """Surrogate training steps (forward, backward, AdamW) at batch 256 on
-    the 7-512-512-512-512-258 network."""
+    """Surrogate training steps (forward, loss, backward, AdamW) at batch 256
+    on the 7-512-512-512-512-258 network: fk_mlp_train_step as the value, the
+    three separate calls beside it."""
     import numpy as np
     import torch
     from paper_2303_14119_amd import flashkin as fk
@@ -184,33 +185,42 @@ def bench_mlp(args):
     torch.cuda.init()
     stream = torch.cuda.current_stream().cuda_stream
     dims, m = S.DIMS, 256
-    net = fk.MLP(dims, max_batch=m, stream=stream)
-    net.set_params(S.init_params(dims, 0))
     rng = np.random.default_rng(0)
     x = torch.from_numpy(rng.uniform(-1, 1, (m, dims[0])).astype(np.float32)).cuda()
     t = torch.from_numpy(rng.standard_normal((m, dims[-1])).astype(np.float32)).cuda()
     flops = sum(2 * m * dims[l] * dims[l + 1] * 3 for l in range(len(dims) - 1))
-    step = 0
-    for _ in range(args.warmup):
-        step += 1
-        net.forward(x.data_ptr(), m)
-        net.backward(t.data_ptr(), m, read_loss=False)
-        net.adamw(step)
-    net.take_loss()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    # the loss of every step is summed on the device and read once at the end
-    for _ in range(args.steps):
-        step += 1
-        net.forward(x.data_ptr(), m)
-        net.backward(t.data_ptr(), m, read_loss=False)
-        net.adamw(step)
-    mean_loss, _ = net.take_loss()
-    el = time.perf_counter() - t0
-    net.close()
-    print(json.dumps({"mode": "mlp", "ms_per_step": round(el * 1e3 / args.steps, 4), "steps": args.steps,
-                      "gflop_per_step": round(flops / 1e9, 4), "tflops": round(flops * args.steps / el / 1e12, 3),
-                      "mean_loss": mean_loss,
+    res = {}
+    for mode in ("separate", "fused"):
+        net = fk.MLP(dims, max_batch=m, stream=stream)
+        net.set_params(S.init_params(dims, 0))
+        step = 0
+
+        def one():
+            nonlocal step
+            step += 1
+            if mode == "fused":
+                net.train_step(x.data_ptr(), t.data_ptr(), m, step)
+            else:
+                net.forward(x.data_ptr(), m)
+                net.backward(t.data_ptr(), m, read_loss=False)
+                net.adamw(step)
+        for _ in range(args.warmup):
+            one()
+        net.take_loss()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        # the loss of every step is summed on the device and read once at the end
+        for _ in range(args.steps):
+            one()
+        mean_loss, _ = net.take_loss()
+        el = time.perf_counter() - t0
+        net.close()
+        res[mode] = (el * 1e3 / args.steps, mean_loss)
+    ms, mean_loss = res["fused"]
+    print(json.dumps({"mode": "mlp", "ms_per_step": round(ms, 4), "steps": args.steps,
+                      "gflop_per_step": round(flops / 1e9, 4), "tflops": round(flops / ms / 1e9, 3),
+                      "mean_loss": mean_loss, "separate_calls_ms_per_step": round(res["separate"][0], 4),
+                      "separate_calls_mean_loss": res["separate"][1],
                       "mfma_bf16_peak_tflops": 2500.0}), flush=True)
 
 

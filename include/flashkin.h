@@ -431,6 +431,19 @@ int fk_mlp_take_loss(fk_mlp* net, double* mean, int64_t* count);
  * with bias-corrected moments; step counts from 1. */
 int fk_mlp_adamw(fk_mlp* net, double lr, double beta1, double beta2, double eps, double weight_decay,
                  int64_t step);
+
+/* One whole training step on a batch: the forward pass, the loss against
+ * target, every gradient and the AdamW step, as fk_mlp_forward,
+ * fk_mlp_backward (loss not read back) and fk_mlp_adamw would do it, with
+ * fewer launches: the loss and its gradient come out of the output layer's
+ * GEMM, and one launch forms every weight gradient and applies AdamW to it
+ * tile by tile, updates the biases and adds up the loss.  x: device FP32
+ * [M][dims[0]]; target: device FP32 [M][dims[n_layers]]; M a multiple of 16
+ * up to max_batch.  The loss joins the running sum of fk_mlp_take_loss and
+ * the gradients stay readable with fk_mlp_get_grads.  Same results as the
+ * three calls up to summation order. */
+int fk_mlp_train_step(fk_mlp* net, const float* x, const float* target, int M, double lr, double beta1,
+                      double beta2, double eps, double weight_decay, int64_t step);
 int fk_mlp_sync(fk_mlp* net);
 
 #ifdef __cplusplus

@@ -30,7 +30,9 @@ enum GemmEpilogue {
     EPI_HIDDEN = 0,   // z = acc + b; store z (FP32), gelu(z) as bf16 [M][N] and [N][M]
     EPI_OUTPUT = 1,   // y = acc + b (FP32)
     EPI_DGRAD = 2,    // dz = acc * gelu'(z); store bf16 [M][N] and [N][M]
-    EPI_WGRAD = 3     // dW = acc (FP32)
+    EPI_WGRAD = 3,    // dW = acc (FP32)
+    EPI_OUTPUT_LOSS = 4   // y = acc + b (FP32), dz = 2 (y - t) / (M dout) on the first dout columns, bf16 in
+                          // both layouts, the tile's sum of squared errors to loss_part
 };
 
 struct GemmArgs {
@@ -48,6 +50,10 @@ struct GemmArgs {
     __bf16* __restrict__ actT;     // bf16 [N][M]
     int ldactT;
     int epi;
+    const float* __restrict__ target;   // EPI_OUTPUT_LOSS: [M][dout]
+    int dout;
+    float gscale;                       // 2 / (M dout)
+    double* __restrict__ loss_part;     // per-tile sums of squared errors
 };
 
 __device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
@@ -70,43 +76,22 @@ struct GemmPair {
 // v_mfma_f32_32x32x16_bf16, splitting K: wave w takes the K steps
 // w, w + 4, w + 8, ... (16 each), so each wave's chain of dependent loads is
 // a quarter of K; the four partial tiles are summed through LDS (fixed
-// order), each wave finishing a quarter of the tile's elements and running
-// their epilogue.  Lane l holds A[row l%32][k0 + 8(l/32)
-// .. +7] and B[col l%32][same k] and accumulates C element e at row
-// 8(e/4) + 4(l/32) + e%4, column l%32 of the tile.
+// order), each wave finishing a quarter of the tile's elements.  Lane l
+// holds A[row l%32][k0 + 8(l/32) .. +7] and B[col l%32][same k] and
+// accumulates C element e at row 8(e/4) + 4(l/32) + e%4, column l%32 of the
+// tile.  On return v[i] (i < 4) is the element at row m0 + 8w + 4(l/32) + i,
+// column n0 + l%32.  Every thread of the workgroup calls it (one barrier).
 constexpr int kGemmTile = 32;
 
-__global__ void __launch_bounds__(256) k_gemm_nt(GemmPair gp)
+__device__ __forceinline__ void gemm_nt_tile(const GemmArgs& g, int m0, int n0, float (&part)[4][16][64],
+                                             float (&v)[4])
 {
-    __shared__ float part[4][16][64];       // every wave's partial tile: [wave][element][lane]
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int second = (int)blockIdx.x >= gp.tiles0 ? 1 : 0;
-    const GemmArgs& g = gp.p[second];
-    const int t = (int)blockIdx.x - (second ? gp.tiles0 : 0);
-    const int m0 = (t / gp.ntn[second]) * kGemmTile;
-    const int n0 = (t % gp.ntn[second]) * kGemmTile;
     const int ra = m0 + (lane & 31), rb = n0 + (lane & 31);
     const int kk = 8 * (lane >> 5);
     const bool a_ok = ra < g.M, b_ok = rb < g.N;
     const __bf16* pa = g.A + (size_t)(a_ok ? ra : 0) * g.lda + kk;
     const __bf16* pb = g.B + (size_t)(b_ok ? rb : 0) * g.ldb + kk;
-    // After the reduction wave w finishes elements 4w .. 4w + 3 of every
-    // lane: rows m0 + 8w + 4 (lane / 32) + i, column n0 + lane % 32.  Their
-    // bias and pre-activation operands are loaded now, alongside the first
-    // operand group, not after the reduction.
-    const int col = n0 + (lane & 31);
-    const bool col_ok = col < g.N;
-    float bias_c = 0.0f, zpre[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    if (col_ok) {
-        if (g.epi == EPI_HIDDEN || g.epi == EPI_OUTPUT) bias_c = g.bias[col];
-        if (g.epi == EPI_DGRAD) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int row = m0 + 8 * w + 4 * (lane >> 5) + i;
-                zpre[i] = g.zin[(size_t)min(row, g.M - 1) * g.ldzin + col];
-            }
-        }
-    }
     f32x16 acc = {0};
     const bf16x8 zero = {0};
     // The wave's K steps (every fourth of 16) in groups of 8: all 16 operand
@@ -131,14 +116,74 @@ __global__ void __launch_bounds__(256) k_gemm_nt(GemmPair gp)
 #pragma unroll
     for (int e = 0; e < 16; ++e) part[w][e][lane] = acc[e];
     __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        // the four waves' partial sums, added in wave order
+        const int e = 4 * w + i;
+        v[i] = ((part[0][e][lane] + part[1][e][lane]) + part[2][e][lane]) + part[3][e][lane];
+    }
+}
+
+__global__ void __launch_bounds__(256) k_gemm_nt(GemmPair gp)
+{
+    __shared__ float part[4][16][64];       // every wave's partial tile: [wave][element][lane]
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int second = (int)blockIdx.x >= gp.tiles0 ? 1 : 0;
+    const GemmArgs& g = gp.p[second];
+    const int t = (int)blockIdx.x - (second ? gp.tiles0 : 0);
+    const int m0 = (t / gp.ntn[second]) * kGemmTile;
+    const int n0 = (t % gp.ntn[second]) * kGemmTile;
+    // This thread finishes rows m0 + 8w + 4 (lane / 32) + i, column
+    // n0 + lane % 32: their bias and pre-activation operands are loaded now,
+    // alongside the first operand group, not after the reduction.
+    const int col = n0 + (lane & 31);
+    const bool col_ok = col < g.N;
+    float bias_c = 0.0f, zpre[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (col_ok) {
+        if (g.epi == EPI_HIDDEN || g.epi == EPI_OUTPUT || g.epi == EPI_OUTPUT_LOSS) bias_c = g.bias[col];
+        if (g.epi == EPI_DGRAD) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = m0 + 8 * w + 4 * (lane >> 5) + i;
+                zpre[i] = g.zin[(size_t)min(row, g.M - 1) * g.ldzin + col];
+            }
+        }
+    }
+    float vv[4];
+    gemm_nt_tile(g, m0, n0, part, vv);
+    if (g.epi == EPI_OUTPUT_LOSS) {
+        // every thread reaches the workgroup sum below
+        __shared__ double sq_w[4];
+        double sq = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = m0 + 8 * w + 4 * (lane >> 5) + i;
+            if (!col_ok || row >= g.M) continue;
+            const float y = vv[i] + bias_c;
+            g.out[(size_t)row * g.ldout + col] = y;
+            float gr = 0.0f;
+            if (col < g.dout) {
+                const float d = y - g.target[(size_t)row * g.dout + col];
+                sq += (double)d * d;
+                gr = g.gscale * d;
+            }
+            const __bf16 h = (__bf16)gr;
+            g.act[(size_t)row * g.ldact + col] = h;
+            g.actT[(size_t)col * g.ldactT + row] = h;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o, 64);
+        if (lane == 0) sq_w[w] = sq;
+        __syncthreads();
+        if (threadIdx.x == 0) g.loss_part[t] = ((sq_w[0] + sq_w[1]) + sq_w[2]) + sq_w[3];
+        return;
+    }
     if (!col_ok) return;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const int e = 4 * w + i;
         const int row = m0 + 8 * w + 4 * (lane >> 5) + i;
         if (row >= g.M) continue;
-        // the four waves' partial sums, added in wave order
-        const float v = ((part[0][e][lane] + part[1][e][lane]) + part[2][e][lane]) + part[3][e][lane];
+        const float v = vv[i];
         switch (g.epi) {
         case EPI_HIDDEN: {
             const float z = v + bias_c;
@@ -287,18 +332,24 @@ struct AdamArgs {
     float lr, b1, b2, eps, c1, c2;   // c1 = 1 - b1^t, c2 = 1 - b2^t
 };
 
+// One AdamW update of element idx from its gradient g; returns the new weight.
+__device__ __forceinline__ float adam_step(float lr, float b1, float b2, float eps, float c1, float c2, float wd,
+                                           float g, float* wp, float* mp, float* vp, int idx)
+{
+    const float m = b1 * mp[idx] + (1.0f - b1) * g;
+    const float v = b2 * vp[idx] + (1.0f - b2) * g * g;
+    mp[idx] = m;
+    vp[idx] = v;
+    const float mh = m / c1, vh = v / c2;
+    float w = wp[idx];
+    w -= lr * (mh / (sqrtf(vh) + eps) + wd * w);
+    wp[idx] = w;
+    return w;
+}
+
 __device__ __forceinline__ float adamw_update(const AdamArgs& a, const AdamSeg& q, int idx)
 {
-    const float g = q.g[idx];
-    const float m = a.b1 * q.m[idx] + (1.0f - a.b1) * g;
-    const float v = a.b2 * q.v[idx] + (1.0f - a.b2) * g * g;
-    q.m[idx] = m;
-    q.v[idx] = v;
-    const float mh = m / a.c1, vh = v / a.c2;
-    float w = q.w[idx];
-    w -= a.lr * (mh / (sqrtf(vh) + a.eps) + q.wd * w);
-    q.w[idx] = w;
-    return w;
+    return adam_step(a.lr, a.b1, a.b2, a.eps, a.c1, a.c2, q.wd, q.g[idx], q.w, q.m, q.v, idx);
 }
 
 // A weight segment is covered by 32 x 32 tiles, one per workgroup: the
@@ -352,6 +403,111 @@ __global__ void k_weight_copies(const float* __restrict__ w, int count, int ld, 
     const int r = idx / ld, c = idx % ld;
     wbf[idx] = (__bf16)w[idx];
     wtbf[(size_t)c * ldT + r] = (__bf16)w[idx];
+}
+
+
+// ---------------------------------------------------------- training step
+// A whole training step in fewer launches (fk_mlp_train_step): the forward
+// GEMMs, the output GEMM with the loss and its gradient in its epilogue
+// (per-tile sums of squared errors), the input-gradient GEMMs, then one
+// launch for every weight gradient dW_l = dZ_{l+1}^T A_l as 32 x 32 tiles
+// (K = the batch, the four-wave tile of k_gemm_nt), each tile written and
+// updated by AdamW in its epilogue (FP32 master, moments, both bf16
+// copies), one workgroup per four bias entries (the gradient from dZ^T,
+// AdamW) and one for the loss.
+
+// Four bf16 values of consecutive rows r0 .. r0 + 3 of a column, stored to a
+// transposed [n][m] array at dst (8-byte aligned) when all four rows exist.
+__device__ __forceinline__ void store_col4(__bf16* dst, const __bf16 (&h)[4], int nrows)
+{
+    if (nrows >= 4) {
+        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+        bf16x4 v = {h[0], h[1], h[2], h[3]};
+        *reinterpret_cast<bf16x4*>(dst) = v;
+    } else {
+        for (int i = 0; i < nrows; ++i) dst[i] = h[i];
+    }
+}
+
+struct WgradAdamArgs {
+    GemmArgs p[kMaxLayers];             // dW_l: A = dZ_{l+1}^T [pad[l+1]][mb], B = A_l^T [pad[l]][mb], K = M
+    int ntn[kMaxLayers];
+    int first[kMaxLayers + 1];          // workgroup ranges of the weight tiles
+    AdamSeg wseg[kMaxLayers];           // the weights' state (g unused)
+    AdamSeg bseg[kMaxLayers];           // the biases' state (g unused)
+    float* wgrad[kMaxLayers];           // out: the weight gradients [pad[l+1]][pad[l]]
+    float* bgrad[kMaxLayers];           // out: the bias gradients
+    int bfirst[kMaxLayers + 1];         // workgroup ranges of the biases (after the tiles), 4 entries each
+    int nl, nloss;
+    const double* loss_part;            // [nloss]
+    double loss_scale;                  // 1 / (M dout)
+    float* loss;
+    double* loss_acc;
+    float lr, b1, b2, eps, c1, c2;
+};
+
+__global__ void __launch_bounds__(256) k_mlp_wgrad_adam(WgradAdamArgs a)
+{
+    __shared__ float part[4][16][64];
+    const int bid = blockIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (bid < a.first[a.nl]) {
+        int s = 0;
+        while (s + 1 < a.nl && bid >= a.first[s + 1]) ++s;
+        const GemmArgs& g = a.p[s];
+        const int tt = bid - a.first[s];
+        const int m0 = (tt / a.ntn[s]) * kGemmTile, n0 = (tt % a.ntn[s]) * kGemmTile;
+        float v[4];
+        gemm_nt_tile(g, m0, n0, part, v);
+        const AdamSeg& q = a.wseg[s];
+        const int col = n0 + (lane & 31);
+        if (col >= g.N) return;
+        const int r0 = m0 + 8 * w + 4 * (lane >> 5);
+        __bf16 h[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            h[i] = (__bf16)0.0f;
+            const int row = r0 + i;
+            if (row >= g.M) continue;
+            const int idx = row * q.ld + col;
+            a.wgrad[s][idx] = v[i];
+            const float wn = adam_step(a.lr, a.b1, a.b2, a.eps, a.c1, a.c2, q.wd, v[i], q.w, q.m, q.v, idx);
+            h[i] = (__bf16)wn;
+            q.wbf[idx] = h[i];
+        }
+        store_col4(q.wtbf + (size_t)col * q.ldT + r0, h, g.M - r0);
+        return;
+    }
+    const int bb = bid - a.first[a.nl];
+    if (bb < a.bfirst[a.nl]) {
+        // four bias entries per workgroup, one wave each: the gradient
+        // db_l[n] = sum_m dZ_{l+1}[m][n] from the transposed copy (strided
+        // lane sums, then the wave's butterfly, as k_mlp_bias_grad), then
+        // AdamW without decay
+        int s = 0;
+        while (s + 1 < a.nl && bb >= a.bfirst[s + 1]) ++s;
+        const AdamSeg& q = a.bseg[s];
+        const int n = (bb - a.bfirst[s]) * 4 + w;
+        if (n >= q.count) return;
+        const __bf16* dzt = a.p[s].A + (size_t)n * a.p[s].lda;
+        float acc = 0.0f;
+        for (int m = lane; m < a.p[s].K; m += 64) acc += (float)dzt[m];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        if (lane == 0) {
+            a.bgrad[s][n] = acc;
+            adam_step(a.lr, a.b1, a.b2, a.eps, a.c1, a.c2, 0.0f, acc, q.w, q.m, q.v, n);
+        }
+        return;
+    }
+    if (threadIdx.x == 0) {
+        double acc = 0.0;
+        for (int b = 0; b < a.nloss; ++b) acc += a.loss_part[b];
+        const float l = (float)(acc * a.loss_scale);
+        *a.loss = l;
+        a.loss_acc[0] += (double)l;
+        a.loss_acc[1] += 1.0;
+    }
 }
 
 }  // namespace fk
@@ -452,7 +608,10 @@ extern "C" int fk_mlp_create(int n_layers, const int32_t* dims, int max_batch, v
     }
     need((void**)&n->loss, 256);
     need((void**)&n->loss_acc, 256);
-    need((void**)&n->loss_part, ((M + kLossRows - 1) / kLossRows) * sizeof(double));
+    // per-workgroup sums of squared errors: the loss kernel's row groups or
+    // the output tiles of the training step's output GEMM
+    const size_t out_tiles = ((M + kGemmTile - 1) / kGemmTile) * ((n->pad[n_layers] + kGemmTile - 1) / kGemmTile);
+    need((void**)&n->loss_part, std::max<size_t>((M + kLossRows - 1) / kLossRows, out_tiles) * sizeof(double));
     for (auto& q : want) off += (q.second + 255) & ~size_t(255);
     if (hipMalloc(&n->pool, off) != hipSuccess) {
         delete n;
@@ -689,6 +848,130 @@ extern "C" int fk_mlp_adamw(fk_mlp* n, double lr, double beta1, double beta2, do
     a.first[a.nseg] = blocks;
     hipLaunchKernelGGL(k_adamw, dim3(blocks), dim3(256), 0, n->stream, a);
     FK_MHIP(n, hipGetLastError());
+    return FK_OK;
+}
+
+extern "C" int fk_mlp_train_step(fk_mlp* n, const float* x, const float* target, int M, double lr, double beta1,
+                                 double beta2, double eps, double weight_decay, int64_t step)
+{
+    if (!n || !x || !target || M < 16 || M > n->max_batch || M % 16 || step < 1)
+        return set_error(n ? &n->err : nullptr, FK_E_INVALID,
+                         "fk_mlp_train_step: batch a multiple of 16 up to max_batch, step >= 1");
+    const int L = n->L, mb = n->max_batch;
+    {
+        const int count = M * n->pad[0];
+        hipLaunchKernelGGL(k_mlp_input, dim3((count + 255) / 256), dim3(256), 0, n->stream, x, M, n->dims[0],
+                           n->pad[0], n->act[0], n->pad[0], n->actT[0], mb);
+    }
+    // forward; the output layer's epilogue forms the loss and dZ_L
+    int loss_tiles = 0;
+    for (int l = 0; l < L; ++l) {
+        GemmArgs g{};
+        g.A = n->act[l];
+        g.lda = n->pad[l];
+        g.B = n->wbf[l];
+        g.ldb = n->pad[l];
+        g.M = M;
+        g.N = n->pad[l + 1];
+        g.K = n->pad[l];
+        g.bias = n->b[l];
+        g.out = n->z[l + 1];
+        g.ldout = n->pad[l + 1];
+        if (l + 1 < L) {
+            g.act = n->act[l + 1];
+            g.ldact = n->pad[l + 1];
+            g.actT = n->actT[l + 1];
+            g.ldactT = mb;
+            g.epi = EPI_HIDDEN;
+        } else {
+            g.act = n->dz[L];
+            g.ldact = n->pad[L];
+            g.actT = n->dzT[L];
+            g.ldactT = mb;
+            g.target = target;
+            g.dout = n->dims[L];
+            g.gscale = (float)(2.0 / ((double)M * n->dims[L]));
+            g.loss_part = n->loss_part;
+            g.epi = EPI_OUTPUT_LOSS;
+            int ntn = 0;
+            loss_tiles = gemm_tiles(g, &ntn);
+        }
+        launch_gemm(n, g);
+    }
+    // input gradients: dZ_{l-1} = (dZ_l W_l) * gelu'(Z_{l-1}), l = L .. 2 (1-based)
+    for (int l = L; l >= 2; --l) {
+        GemmArgs d{};
+        d.A = n->dz[l];
+        d.lda = n->pad[l];
+        d.B = n->wtbf[l - 1];
+        d.ldb = n->pad[l];
+        d.M = M;
+        d.N = n->pad[l - 1];
+        d.K = n->pad[l];
+        d.zin = n->z[l - 1];
+        d.ldzin = n->pad[l - 1];
+        d.act = n->dz[l - 1];
+        d.ldact = n->pad[l - 1];
+        d.actT = n->dzT[l - 1];
+        d.ldactT = mb;
+        d.epi = EPI_DGRAD;
+        launch_gemm(n, d);
+    }
+    // weight gradients with AdamW, bias gradients with AdamW, the loss
+    WgradAdamArgs a{};
+    a.nl = L;
+    int tiles = 0;
+    for (int l = 0; l < L; ++l) {
+        GemmArgs& g = a.p[l];
+        g.A = n->dzT[l + 1];
+        g.lda = mb;
+        g.B = n->actT[l];
+        g.ldb = mb;
+        g.M = n->pad[l + 1];
+        g.N = n->pad[l];
+        g.K = M;
+        g.epi = EPI_WGRAD;
+        a.first[l] = tiles;
+        tiles += gemm_tiles(g, &a.ntn[l]);
+        AdamSeg& q = a.wseg[l];
+        q.w = n->w[l];
+        q.m = n->mw[l];
+        q.v = n->vw[l];
+        q.wbf = n->wbf[l];
+        q.wtbf = n->wtbf[l];
+        q.ld = n->pad[l];
+        q.ldT = n->pad[l + 1];
+        q.count = n->pad[l + 1] * n->pad[l];
+        q.wd = (float)weight_decay;
+        AdamSeg& bq = a.bseg[l];
+        bq.w = n->b[l];
+        bq.m = n->mb[l];
+        bq.v = n->vb[l];
+        bq.count = n->pad[l + 1];
+        a.wgrad[l] = n->gw[l];
+        a.bgrad[l] = n->gb[l];
+    }
+    a.first[L] = tiles;
+    int bblocks = 0;
+    for (int l = 0; l < L; ++l) {
+        a.bfirst[l] = bblocks;
+        bblocks += (n->pad[l + 1] + 3) / 4;
+    }
+    a.bfirst[L] = bblocks;
+    a.loss_part = n->loss_part;
+    a.nloss = loss_tiles;
+    a.loss_scale = 1.0 / ((double)M * n->dims[L]);
+    a.loss = n->loss;
+    a.loss_acc = n->loss_acc;
+    a.lr = (float)lr;
+    a.b1 = (float)beta1;
+    a.b2 = (float)beta2;
+    a.eps = (float)eps;
+    a.c1 = (float)(1.0 - std::pow(beta1, (double)step));
+    a.c2 = (float)(1.0 - std::pow(beta2, (double)step));
+    hipLaunchKernelGGL(k_mlp_wgrad_adam, dim3(tiles + bblocks + 1), dim3(256), 0, n->stream, a);
+    FK_MHIP(n, hipGetLastError());
+    n->last_m = M;
     return FK_OK;
 }
 

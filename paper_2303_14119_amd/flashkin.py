@@ -138,6 +138,8 @@ SIGNATURES = {
     "fk_mlp_forward": (C.c_int, [_vp, _vp, C.c_int, _vp]),
     "fk_mlp_backward": (C.c_int, [_vp, _vp, C.c_int, _P(C.c_float)]),
     "fk_mlp_adamw": (C.c_int, [_vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int64]),
+    "fk_mlp_train_step": (C.c_int, [_vp, _vp, _vp, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
+                                    C.c_double, C.c_int64]),
     "fk_mlp_take_loss": (C.c_int, [_vp, _P(C.c_double), _P(C.c_int64)]),
     "fk_mlp_sync": (C.c_int, [_vp]),
 }
@@ -491,6 +493,10 @@ class MLP:
 
     def adamw(self, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=1e-4):
         self._chk(fk_mlp_adamw(self._h, lr, beta1, beta2, eps, weight_decay, int(step)))
+
+    def train_step(self, x_ptr, t_ptr, m, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=1e-4):
+        """Forward, loss, gradients and AdamW on one batch (fk_mlp_train_step)."""
+        self._chk(fk_mlp_train_step(self._h, x_ptr, t_ptr, int(m), lr, beta1, beta2, eps, weight_decay, int(step)))
 
     def sync(self):
         self._chk(fk_mlp_sync(self._h))

@@ -213,9 +213,9 @@ class Surrogate:
                 # cosine decay of the learning rate over the run
                 frac = ep / max(1, epochs - 1)
                 lr_t = lr * (0.05 + 0.95 * 0.5 * (1 + math.cos(math.pi * frac)))
-                self.net.forward(xs[lo:lo + m].data_ptr(), m)
-                self.net.backward(ys[lo:lo + m].data_ptr(), m, read_loss=False)   # no per-step sync
-                self.net.adamw(self.step, lr=lr_t, weight_decay=weight_decay)
+                # forward, loss, gradients and AdamW in one call; no per-step sync
+                self.net.train_step(xs[lo:lo + m].data_ptr(), ys[lo:lo + m].data_ptr(), m, self.step, lr=lr_t,
+                                    weight_decay=weight_decay)
             rec = {"epoch": ep, "train": self.net.take_loss()[0]}
             if Xval is not None and (ep % 20 == 19 or ep == epochs - 1):
                 rec["val"] = float(np.mean((self.predict(Xval) - Yval) ** 2))

@@ -139,3 +139,85 @@ def test_training_reduces_loss(env):
     assert count == 4 and 0.0 < mean < losses[0]
     assert net.take_loss() == (0.0, 0)
     net.close()
+
+
+# ---------------------------------------------------------------- fused step
+
+@pytest.mark.parametrize("dims,m", [(DIMS, 256), ([3, 40, 33, 7], 32), ([5, 64, 70], 48), (DIMS, 16)])
+def test_train_step_matches_oracle_and_the_separate_calls(env, dims, m):
+    """fk_mlp_train_step (loss in the output GEMM, AdamW in the weight-gradient
+    tiles) against the FP64
+    oracle's loss and gradients (1e-2, as the separate calls), against the
+    separate calls' loss (1e-5) and gradients, and its AdamW step against the
+    oracle's step applied to its own gradients (as the separate AdamW).  The
+    48- and 16-row batches end in half tiles."""
+    torch, fk = env
+    p, x, t = make_case(dims, m, seed=3 * len(dims) + m)
+    mb = max(m, 64)
+    sep, fused = fk.MLP(dims, max_batch=mb), fk.MLP(dims, max_batch=mb)
+    sep.set_params(p)
+    fused.set_params(p)
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    sep.forward(xd.data_ptr(), m)
+    loss_sep = sep.backward(td.data_ptr(), m)
+    g_sep = sep.grads()
+    fused.take_loss()
+    fused.train_step(xd.data_ptr(), td.data_ptr(), m, 1, lr=1e-3, weight_decay=0.01)
+    loss, count = fused.take_loss()
+    g = fused.grads()
+    loss_ref, g_ref = omlp.loss_and_grads(p, dims, x, t)
+    print(dims, m, "loss", loss, loss_sep, loss_ref)
+    assert count == 1 and loss == pytest.approx(loss_sep, rel=1e-5)
+    assert abs(loss - loss_ref) < 1e-2 * loss_ref
+    for l, (sw, sb) in enumerate(layer_slices(dims)):
+        ew, eb = rel_l2(g[sw], g_ref[sw]), rel_l2(g[sb], g_ref[sb])
+        sw_, sb_ = rel_l2(g[sw], g_sep[sw]), rel_l2(g[sb], g_sep[sb])
+        print("  layer", l, "vs oracle", ew, eb, "vs separate", sw_, sb_)
+        assert ew < 1e-2 and eb < 1e-2, (l, ew, eb)
+        assert sw_ < 5e-3 and sb_ < 5e-3, (l, sw_, sb_)
+    z = np.zeros(p.size)
+    want, _, _ = omlp.adamw(p.astype(np.float64), g.astype(np.float64), z, z, 1, dims, 1e-3, 0.9, 0.999, 1e-8, 0.01)
+    assert np.allclose(fused.params().astype(np.float64), want, rtol=2e-6, atol=1e-7)
+    sep.close()
+    fused.close()
+
+
+def test_train_step_trains_like_the_separate_calls(env):
+    """300 steps of the smooth regression of test_training_reduces_loss with
+    the fused step: the loss falls tenfold and ends within 10% of the
+    separate calls' run from the same start."""
+    torch, fk = env
+    rng = np.random.default_rng(0)
+    m = 256
+    x = rng.uniform(-1, 1, (1024, 5)).astype(np.float32)
+    basis = rng.standard_normal((5, 258)).astype(np.float32)
+    t = np.sin(x @ basis).astype(np.float32)
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    p0 = omlp.init_params(DIMS, 1).astype(np.float32)
+    runs = {}
+    for mode in ("separate", "fused"):
+        net = fk.MLP(DIMS, max_batch=m)
+        net.set_params(p0)
+        net.take_loss()
+        first = last = None
+        for step in range(1, 301):
+            lo = (step - 1) % 4 * m
+            if mode == "fused":
+                net.train_step(xd[lo:lo + m].data_ptr(), td[lo:lo + m].data_ptr(), m, step, lr=1e-3,
+                               weight_decay=1e-4)
+            else:
+                net.forward(xd[lo:lo + m].data_ptr(), m)
+                net.backward(td[lo:lo + m].data_ptr(), m, read_loss=False)
+                net.adamw(step, lr=1e-3, weight_decay=1e-4)
+            if step == 1:
+                first = net.take_loss()[0]
+            if step == 300:
+                last = net.take_loss()[0]
+        runs[mode] = (first, last)
+        net.close()
+    print(runs)
+    f0, f1 = runs["fused"]
+    s0, s1 = runs["separate"]
+    assert f0 == pytest.approx(s0, rel=1e-5)
+    assert f1 < 0.1 * f0
+    assert abs(f1 - s1) < 0.1 * s1
