@@ -90,3 +90,25 @@ def test_noalloc_reports_cfl_and_rejects_oversized(env):
     assert rc == fk.E_INVALID and b"32 MiB" in fk.fk_last_error(None)
     p = fk.make_params(cfg, "f32")
     assert fk.fk_step_noalloc(C.byref(p), None, x.data_ptr(), x.data_ptr(), 0.0, 0.0, 0, 1, None, None) == fk.E_INVALID
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_noalloc_second_order_and_collisions(env, dtype):
+    """The same bitwise agreement with the second-order scheme (both split
+    orders: an odd number of steps from step 0) and with the collision
+    term."""
+    torch, fk = env
+    base = dict(nx=64, nvx=48, nvy=64, length=0.5e-3, ey=-5e6, delta_max=2.5, a_max_ev=400.0)
+    cases = [
+        (W.config(scheme=fk.SCHEME_LIMITED2, r_refl=0.1, **base), 2e-6, 21),
+        (W.config(physics_mask=W.ALL | W.BGK, t_e_ev=2.0, ln_lambda=10.0, **base), 2e-6, 19),
+    ]
+    for m, (cfg, sigma0, steps) in enumerate(cases):
+        f0 = W.random_state((cfg["nx"], cfg["nvx"], cfg["nvy"]), seed=60 + m, scale=1e3)
+        f0 = f0.astype(np.float32 if dtype == "f32" else np.float64)
+        fr, sr = context_run(torch, fk, cfg, dtype, f0, sigma0, steps)
+        fn, sn, flags = noalloc_run(torch, fk, cfg, dtype, f0, sigma0, steps)
+        assert flags == 0
+        assert np.array_equal(fn, fr), m
+        for q in ("step", "sigma", "sigma_lo", "g_pe", "g_see", "g_top", "emitted", "loss_v", "n_total", "resid"):
+            assert sn[q] == sr[q], (m, q, sn[q], sr[q])
