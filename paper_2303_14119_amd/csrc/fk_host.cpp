@@ -117,13 +117,11 @@ int derive_layout(const fk_params* p, Layout* L, std::string* why)
     l.block = ((p->nvy + 63) / 64) * 64;
     l.scheme = p->scheme;
     if (p->scheme == FK_SCHEME_LIMITED2) {
-        // second order: 8 rows (FP32) or 4 (FP64) where the v_y exchange of
-        // ti + 4 rows fits; a single launch over every tile
+        // second order: 4-row tiles by default (four waves per SIMD; 8-row
+        // tiles hold three and ran slower at every chunk length measured);
+        // the tiles with a fast body and the rest take one launch each
         int ti = p->tile_rows;
-        if (ti == 0) {
-            ti = l.elem == 4 ? 8 : 4;
-            while (ti > 4 && sweep2_lds(ti, l.block, 4, l.elem) > kLdsBudget) ti /= 2;
-        }
+        if (ti == 0) ti = 4;
         if (ti != 4 && ti != 8) return bad("FK_SCHEME_LIMITED2 takes tile_rows 4 or 8");
         if (sweep2_lds(ti, l.block, 4, l.elem) > kLdsBudget)
             return bad("FK_SCHEME_LIMITED2: the v_y exchange does not fit in LDS (nvy up to 768 in FP32 with 4-row tiles, "
@@ -132,11 +130,12 @@ int derive_layout(const fk_params* p, Layout* L, std::string* why)
         l.n_it = (p->nvx + ti - 1) / ti;
         int kc = p->tile_planes;
         if (kc == 0) {
-            const int target = 1024;
-            int nkc = (target + l.n_it - 1) / l.n_it;
-            kc = (p->nx + nkc - 1) / nkc;
-            kc = std::max(16, std::min(kc, 128));
-            while (kc > 4 && sweep2_lds(ti, l.block, kc, l.elem) > kLdsBudget) kc = kc > 16 ? kc - 16 : kc / 2;
+            // short chunks: the sweep is bound by the vector ALU, and many
+            // small workgroups balance the slower edge tiles; 32 planes, or
+            // 16 where that leaves fewer than 2048 workgroups
+            kc = 32;
+            if ((int64_t)l.n_it * ((p->nx + 31) / 32) < 2048) kc = 16;
+            while (kc > 4 && sweep2_lds(ti, l.block, kc, l.elem) > kLdsBudget) kc /= 2;
         }
         if (kc > p->nx) kc = p->nx;
         l.kc = kc;

@@ -892,7 +892,9 @@ int create_impl(const fk_params* p, void* stream, void* fa, void* fb, fk_ctx** o
     std::string why;
     int rc = derive_layout(p, &L, &why);
     if (rc) return set_error(nullptr, rc, why);
-    if (p->tile_planes == 0) choose_planes(p, &L);
+    // the chunk length from the upwind sweep's occupancy; the second-order
+    // sweep keeps its short chunks (it is bound by the vector ALU)
+    if (p->tile_planes == 0 && p->scheme == FK_SCHEME_UPWIND) choose_planes(p, &L);
     if ((fa == nullptr) != (fb == nullptr)) return set_error(nullptr, FK_E_INVALID, "borrowed buffers: give both or neither");
     if (fa && fa == fb) return set_error(nullptr, FK_E_INVALID, "borrowed buffers must differ");
     fk_ctx* c = new (std::nothrow) fk_ctx();
@@ -1327,7 +1329,9 @@ extern "C" int fk_step_noalloc(const fk_params* p, void* stream, void* f_a, void
     Layout L;
     int rc = derive_layout(p, &L, nullptr);
     if (rc) return set_static_error(rc, "fk_step_noalloc: invalid parameters (fk_validate gives the reason)");
-    if (p->tile_planes == 0) choose_planes(p, &L);
+    // the chunk length from the upwind sweep's occupancy; the second-order
+    // sweep keeps its short chunks (it is bound by the vector ALU)
+    if (p->tile_planes == 0 && p->scheme == FK_SCHEME_UPWIND) choose_planes(p, &L);
     const size_t need = carve_buffers(*p, L, nullptr, nullptr);
     if (need > kScratchBytes)
         return set_static_error(FK_E_INVALID,
