@@ -183,11 +183,11 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
         }
     }
     // wall, top, velocity-box and absorbed partials: compensated sums.  The
-    // n_it tile partials go to wave 0 and the nwg box-loss partials to wave
-    // 1 (wave 0 in a one-wave workgroup), strided over the lanes; the other
-    // waves hold zeros, which leave a compensated sum unchanged.
+    // n_it tile partials go to wave 0, strided over its lanes (the other
+    // waves hold zeros, which leave a compensated sum unchanged); the nwg
+    // box-loss partials (one per sweep workgroup, thousands) are strided
+    // over the whole workgroup.
     constexpr int kParts = 6;       // primary, secondary, top, box loss, absorbed at wall / top
-    const int lv_wave = nw > 1 ? 1 : 0;
     CSum part[kParts];
     if (wave == 0) {
         for (int u = lane; u < a.n_it; u += 64) {
@@ -200,15 +200,15 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
             }
         }
     }
-    if (a.advance && wave == lv_wave) {
-        // eight loads in flight per lane before their adds
-        for (int w0 = lane; w0 < a.nwg; w0 += 64 * 8) {
-            double v[8];
+    if (a.advance) {
+        // four loads in flight per thread before their adds
+        for (int w0 = t; w0 < a.nwg; w0 += T * 4) {
+            double v[4];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) v[q] = a.part_lv[min(w0 + 64 * q, a.nwg - 1)];
+            for (int q = 0; q < 4; ++q) v[q] = a.part_lv[min(w0 + T * q, a.nwg - 1)];
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
-                if (w0 + 64 * q < a.nwg) cadd(part[3], v[q]);
+            for (int q = 0; q < 4; ++q)
+                if (w0 + T * q < a.nwg) cadd(part[3], v[q]);
         }
     }
 
@@ -231,7 +231,7 @@ __device__ __forceinline__ void field_block(const FieldArgs& a, double* sh)
             part[5] = wave_csum(part[5]);
         }
     }
-    if (wave == lv_wave) part[3] = wave_csum(part[3]);
+    part[3] = wave_csum(part[3]);
     if (lane == 0) {
         double* r = red + wave * (kParts + 1) * 2;
 #pragma unroll

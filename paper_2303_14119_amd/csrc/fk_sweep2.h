@@ -907,6 +907,41 @@ __global__ void __launch_bounds__(MAXB, (sweep2_waves<T, TI>())) k_sweep2_fast(S
     }
 }
 
+// Every tile in one launch: workgroups [0, n_gen) (a multiple of 8, the
+// last ones idle if needed) take the other tiles with the generic bodies and
+// start first; the rest take the fast tiles.  Each part keeps its own
+// XCD-aware order (n_gen a multiple of 8 leaves every workgroup on the XCD
+// its own part assigns it).
+template <typename T, int TI, int MAXB, bool REV>
+__global__ void __launch_bounds__(MAXB, (sweep2_waves<T, TI>())) k_sweep2_all(SweepArgs<T> a, const int* tiles,
+                                                                            int n_fast, int n_generic, int n_gen,
+                                                                            int n_kc)
+{
+    extern __shared__ double smem[];
+    const int b = blockIdx.x;
+    if (b < n_gen) {
+        const int count = n_generic * n_kc;
+        const int wg = xcd_remap(b, n_gen);
+        if (wg >= count) return;
+        const int it = tiles[n_fast + wg % n_generic];
+        const int kci = wg / n_generic;
+        if (REV) sweep2_reversed<T, TI>(a, it, kci, smem, threadIdx.x, blockDim.x);
+        else sweep2_forward<T, TI>(a, it, kci, smem, threadIdx.x, blockDim.x);
+        return;
+    }
+    const int wg = xcd_remap(b - n_gen, (int)gridDim.x - n_gen);
+    const int it = tiles[wg % n_fast];
+    const int kci = wg / n_fast;
+    const bool up = tile2_side(it, TI, a.nvx) > 0;
+    if (REV) {
+        if (up) sweep2_reversed_fast<T, TI, true>(a, it, kci, smem, threadIdx.x, blockDim.x);
+        else sweep2_reversed_fast<T, TI, false>(a, it, kci, smem, threadIdx.x, blockDim.x);
+    } else {
+        if (up) sweep2_forward_fast<T, TI, true>(a, it, kci, smem, threadIdx.x, blockDim.x);
+        else sweep2_forward_fast<T, TI, false>(a, it, kci, smem, threadIdx.x, blockDim.x);
+    }
+}
+
 // The other tiles (edge tiles, tiles whose rows straddle v_x = 0): the
 // generic bodies with per-row masks.
 template <typename T, int TI, int MAXB, bool REV>
