@@ -143,6 +143,40 @@ def test_large_grid_two_steps(fk):
         assert rel(st[q], orc[q]) <= 1e-6, q
 
 
+def test_grid_past_two_to_the_31_cells(fk):
+    """14720 x 384 x 384 = 2.17e9 cells, past 2^31 (8.7 GB per FP32 f
+    buffer), at the 4096 x 384 x 384 run's cell size: every flat offset on
+    the path must be 64-bit.  Two FP32 steps from a separable state against
+    the FP64 oracle: sampled planes (the first and last two, both sides of
+    chunk boundaries, planes past 2^31 / (384 x 384) = 14564) to 1e-6
+    relative L2, the wall fluxes and the electron total to 1e-6."""
+    nx = 14720
+    cfg = W.config(nx=nx, nvx=384, nvy=384, length=1e-3 * nx / 4096, ey=-6e6, delta_max=2.8, a_max_ev=450.0)
+    assert nx * 384 * 384 > 2 ** 31
+    f0 = separable_state((nx, 384, 384), seed=13, scale=2e3)
+    with fk.Solver(cfg, "f32") as s:
+        s.write_state(f0, 3e-6, 0.0, 0)
+        s.step(2)
+        s.sync()
+        g, st = s.f(), s.state()
+    planes = [0, 1, 127, 128, 129, 7360, 14563, 14564, 14565, nx - 2, nx - 1]
+    gs = g[planes].astype(np.float64)
+    del g
+    o = Oracle(cfg)
+    o.set_state(f0, 3e-6, 0)
+    del f0
+    o.step(2)
+    orc = o.record()
+    ref = o.f()
+    o.close()
+    rs = ref[planes]
+    del ref
+    for m, k in enumerate(planes):
+        assert rel_l2(gs[m], rs[m]) <= 1e-6, k
+    for q in ("g_pe", "g_see", "n_total"):
+        assert rel(st[q], orc[q]) <= 1e-6, q
+
+
 def test_large_grid_charged_profile_fifty_steps(fk):
     """4096 x 384 x 384 (the largest single-GPU workload) from a charged
     state built by fk_warm_start: an enclosed-charge profile falling from
