@@ -1,8 +1,9 @@
 """GPU parity of the second-order scheme (FK_SCHEME_LIMITED2) with the FP64
 oracle's scheme 1: minmod-limited flux-form sweeps, the split order reversed
-on odd steps.  The library runs a step as two fused sweep launches (the
-tiles with a fast body, then the edge and mixed-direction tiles): forward
-bodies on even steps, reversed bodies on odd ones, two-cell halos.
+on odd steps.  The library runs a step's sweep as one fused launch (the
+workgroups of the edge and mixed-direction tiles first, then those of the
+tiles with a fast body): forward bodies on even steps, reversed bodies on
+odd ones, two-cell halos.
 
 Cases cover 4- and 8-row tiles, short x chunks (so chunk boundaries and the
 halo planes of the reversed body are exercised), ragged v_x and v_y, odd
