@@ -85,7 +85,8 @@ enum {
                              * a reversed step the electrons absorbed at the wall and at x = L are those
                              * of the array the x sweep transports; the yield, emission row and
                              * reflection still come from f^n.  FK_F32 or FK_F64; not with FK_PHYS_BGK or
-                             * in a batch (FK_E_INVALID) */
+                             * in a batch (FK_E_INVALID).  Tiles of 4 or 8 v_x rows; nvy up to 768 (FK_F32)
+                             * or 384 (FK_F64) with 4 rows, 512 or 256 with 8 */
 };
 
 /* error codes */
@@ -124,7 +125,8 @@ typedef struct {
     double ex_external;      /* uniform E_x added to the self field, V/m */
     int32_t trace_stride;    /* record observables every trace_stride steps (>= 1) */
     int32_t trace_cap;       /* records held on the device between drains (>= 1) */
-    int32_t tile_rows;       /* v_x rows per tile: 4, 8, 12 or 16 (12 and 16: FK_F32, nvy <= 512), 0 = library choice */
+    int32_t tile_rows;       /* v_x rows per tile: 4, 8, 12 or 16 (12: FK_F32, nvy <= 512; 16: FK_F32, nvy <= 448;
+                              * 8: nvy <= 960 in FK_F32, 448 in FK_F64), 0 = library choice */
     int32_t tile_planes;     /* x planes per tile; 0: chosen at creation from the sweep kernel's occupancy: the longest run (16..128) that keeps 8 waves resident per compute unit, or all a unit holds, with the workgroups spread evenly (fk_validate reports a host-side estimate, fk_query the choice); batch instances get 16 */
     double t_e_ev;           /* FK_PHYS_BGK: temperature of the collisional equilibrium (Eq 4-5), eV, > 0 */
     double ln_lambda;        /* FK_PHYS_BGK: Coulomb logarithm of Eq 4 (the paper: 10), > 0 */

@@ -113,10 +113,15 @@ RAGGED = [
     (5, 9, 700, W.ALL, -5e6, 0.0, 0),
     (3, 6, 960, W.ALL & ~W.SRC, -4e6, 1e5, 0),
 ]
+# the widest v_y block (16 waves), FP32 only: FP64 tiles of it do not fit in LDS
+WIDEST = [(2, 5, 1024, W.ALL, -5e6, 0.0, 0), (3, 9, 1009, W.ALL & ~W.SRC, -4e6, 1e5, 1)]
 
 
-@pytest.mark.parametrize("case", RAGGED, ids=[f"{c[0]}x{c[1]}x{c[2]}-m{c[3]}" for c in RAGGED])
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
+RAGGED_CASES = [(c, d) for d in ("f64", "f32") for c in RAGGED] + [(c, "f32") for c in WIDEST]
+
+
+@pytest.mark.parametrize("case,dtype", RAGGED_CASES,
+                         ids=[f"{d}-{c[0]}x{c[1]}x{c[2]}-m{c[3]}" for c, d in RAGGED_CASES])
 def test_ragged_random_state(fk, case, dtype):
     nx, nvx, nvy, mask, ey, exe, norm = case
     cfg = W.config(nx=nx, nvx=nvx, nvy=nvy, length=nx * 2e-6, ey=ey, delta_max=2.5,

@@ -95,6 +95,35 @@ def test_random_state_matches_oracle(fk, case, dtype, start):
     assert st["step"] == start + steps
 
 
+WIDEST = [("f32", 4, 768), ("f32", 8, 512), ("f64", 4, 384), ("f64", 8, 256)]
+
+
+@pytest.mark.parametrize("dtype,ti,nvy", WIDEST, ids=[f"{d}-ti{t}-{n}" for d, t, n in WIDEST])
+def test_widest_v_y_blocks(fk, dtype, ti, nvy):
+    """The widest v_y block each tile height and precision accepts (the
+    v_y exchange at its LDS limit), with a ragged last v_x tile and short x
+    chunks, from an odd step (reversed bodies first)."""
+    cfg = W.config(nx=6, nvx=11, nvy=nvy, length=12e-6, ey=-4e6, delta_max=2.5, a_max_ev=400.0,
+                   x_src_lo=1e-6, x_src_hi=5e-6, j_src=1e7, cfl=0.8, scheme=1)
+    f0 = W.random_state((6, 11, nvy), seed=nvy + ti, scale=1e3)
+    if dtype == "f32":
+        f0 = f0.astype(np.float32).astype(np.float64)
+    o = Oracle(cfg)
+    o.set_state(f0, 3e-6, 1)
+    with fk.Solver(cfg, dtype, tile_rows=ti, tile_planes=4) as s:
+        assert s.info["tile_rows"] == ti
+        s.write_state(f0, 3e-6, 0.0, 1)
+        o.step(20)
+        s.step(20)
+        s.sync()
+        g, st = s.f(), s.state()
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    assert rel_l2(g, o.f()) <= tol
+    assert rel(st["sigma"] + st["sigma_lo"], o.record()["sigma"]) <= (1e-11 if dtype == "f64" else 1e-5)
+    with pytest.raises(fk.FlashkinError):
+        fk.Solver(dict(cfg, nvy=nvy + 1), dtype, tile_rows=ti)
+
+
 def test_second_order_differs_from_first_order(fk):
     """The scheme switch takes effect: the same state advanced by the two
     schemes ends apart by far more than rounding."""
