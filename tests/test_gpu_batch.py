@@ -94,6 +94,49 @@ def test_batch_is_bitwise_a_standalone_context(fk, single, threads):
                 assert ss[q] == sb[q], q
 
 
+def edge_instances():
+    """Instances at the v_y block edges (64, 128, 192 and 256 lanes and one
+    past each) and at the batch's maximum width, with N_vx apart from N_vy,
+    a single v_y cell, and one x plane."""
+    shapes = [(17, 9, 256), (12, 30, 193), (9, 13, 192), (20, 7, 129), (11, 24, 128), (15, 5, 65),
+              (8, 19, 64), (6, 3, 1), (1, 10, 100)]
+    return [W.config(nx=nx, nvx=nvx, nvy=nvy, length=nx * 3e-6, ey=-4e6 - 1e5 * k, delta_max=2.5,
+                     a_max_ev=400.0, x_src_lo=1e-6, x_src_hi=5e-6, j_src=1e7, cfl=0.8)
+            for k, (nx, nvx, nvy) in enumerate(shapes)]
+
+
+@pytest.mark.parametrize("single,threads", [(False, 256), (True, 256), (True, 192)])
+def test_batch_block_edges_match_oracle(fk, single, threads):
+    """Instances at every v_y block edge and at the largest accepted width,
+    in each launch mode (192-thread workgroups fall back to 256 since an
+    instance is wider than 192), against the FP64 oracle from random
+    states; a width past the maximum is refused."""
+    cfgs = edge_instances()
+    steps = 30
+    states = [W.random_state((c["nx"], c["nvx"], c["nvy"]), seed=40 + m, scale=1e1).astype(np.float32)
+              for m, c in enumerate(cfgs)]
+    with fk.Batch(cfgs, single_launch=single, single_threads=threads) as b:
+        info = b.info()
+        assert info["single_threads"] == (256 if single else 0)
+        for m, v in enumerate(b.views):
+            v.write_state(states[m], 2e-6, 0.0, 0)
+        b.step(steps)
+        b.sync()
+        outs = [(v.f(), v.state()) for v in b.views]
+    for m, (c, (fb, st)) in enumerate(zip(cfgs, outs)):
+        o = Oracle(c)
+        o.set_state(states[m].astype(np.float64), 2e-6, 0)
+        o.step(steps)
+        orc = o.record()
+        assert st["step"] == steps
+        assert rel_l2(fb, o.f()) < 1e-5, (m, c["nx"], c["nvx"], c["nvy"])
+        for q in ("g_pe", "g_see", "n_total"):
+            assert abs(st[q] - orc[q]) <= 1e-5 * abs(orc[q]) + 1e-30, (m, q)
+        assert abs(st["sigma"] + st["sigma_lo"] - orc["sigma"]) <= 1e-5 * abs(orc["sigma"]) + 1e-30, m
+    with pytest.raises(fk.FlashkinError):
+        fk.Batch([dict(cfgs[0], nvy=257)])
+
+
 def test_batch_views_refuse_single_steps(fk):
     with fk.Batch(small_instances(3, 2)) as b:
         with pytest.raises(fk.FlashkinError) as ei:
