@@ -108,6 +108,10 @@ RAGGED = [
     (21, 17, 131, W.ALL & ~W.SRC, 4e6, -1e5, 0),
     (5, 7, 3, W.ALL, -5e6, 0.0, 0),
     (1, 4, 1, W.ALL, -5e6, 0.0, 0),
+    # a single v_x row (v_x = 0 only: no wall flux) and two rows (one per sign)
+    (4, 1, 9, W.ALL, -5e6, 0.0, 0),
+    (6, 1, 1, W.ALL, -5e6, 2e5, 1),
+    (3, 2, 2, W.ALL, -5e6, 0.0, 0),
     (64, 40, 257, W.VX | W.VY, -3e6, 2e6, 0),
     # v_y blocks above 512 lanes (the 1024-thread kernels), up to the maximum
     (5, 9, 700, W.ALL, -5e6, 0.0, 0),

@@ -59,6 +59,8 @@ CASES = [
     (5, 7, 3, 0, 0, {}),
     (1, 4, 1, 0, 0, {}),
     (30, 24, 200, 8, 7, dict(physics_mask=W.X | W.SEE | W.SRC)),
+    (4, 1, 9, 0, 0, {}),
+    (3, 2, 2, 4, 4, dict(r_refl=0.2)),
 ]
 
 
