@@ -106,6 +106,11 @@ FULL = [
     (23, 48, 100, 12),
     (13, 45, 384, 16),
     (17, 41, 330, 12),
+    # the widest blocks (FP64 up to 960 lanes) and degenerate velocity grids
+    (4, 7, 960, 0),
+    (3, 5, 1024, 4),
+    (6, 1, 9, 0),
+    (4, 2, 2, 0),
 ]
 
 
@@ -115,6 +120,8 @@ def test_full_step_with_collisions(fk, case, dtype):
     nx, nvx, nvy, ti = case
     if dtype == "f64" and ti in (12, 16):
         pytest.skip("12- and 16-row tiles are FP32 only")
+    if dtype == "f64" and nvy > 960:
+        pytest.skip("FP64 v_y blocks end at 960 lanes")
     cfg = W.config(nx=nx, nvx=nvx, nvy=nvy, length=nx * 2e-6, ey=-4e6, delta_max=2.5, a_max_ev=400.0,
                    physics_mask=(W.ALL & ~W.SELF) | W.BGK, ex_external=1e5, x_src_lo=1e-6, x_src_hi=5e-6,
                    j_src=1e7, cfl=0.8, t_e_ev=40.0, ln_lambda=10.0)
