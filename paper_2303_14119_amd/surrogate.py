@@ -6,8 +6,8 @@ run's parameters (|E_y|, delta_max, A_max, T_se, L) and its grid
 resolution (N_x, N_v) to its saturated
 x-resolved enclosed charge sigma_enc(x) on 256 points plus the primary and
 secondary fluxes; its prediction initialises a new run, which then continues
-to saturation.  The plain cold start stays the fallback and the judge of the
-prediction's error.
+to saturation.  The plain cold start stays the fallback and the reference
+against which the prediction's error is measured.
 
 Every step runs in the library's kernels: the batched solver generates the
 data, fk_read_profile resamples it, the network trains with fk_mlp_* and

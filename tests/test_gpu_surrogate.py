@@ -8,7 +8,7 @@ with the library's kernels, and then:
     could guess;
   * a held-out run warm-started from the prediction passes the Section 2
     saturation test in fewer steps than the cold start, and both runs end
-    at the same state (the cold run is the judge): after the test passes
+    at the same state (the cold run is the reference): after the test passes
     each run goes on for another 200 ps, and the two sigma_enc(x) profiles
     then agree to 1e-3 (relative L2).
 The committed weights (trained on the batched sweep of the parameter box,
