@@ -332,8 +332,13 @@ void launch_sweep_b(const fk_ctx* c, int from, hipStream_t s)
     if (c->L.n_fast > 0) {
         a.tile_list = c->b.tiles;
         a.n_list = c->L.n_fast;
-        hipLaunchKernelGGL((k_sweep<T, TI, MAXB, BGK>), dim3(c->L.n_fast * c->L.n_kc), dim3(c->L.block),
-                           c->L.lds_sweep, s, a);
+        // inner rows streamed where the stores are non-temporal too (rows on 128-byte lines)
+        if (a.store_nt)
+            hipLaunchKernelGGL((k_sweep<T, TI, MAXB, BGK, true>), dim3(c->L.n_fast * c->L.n_kc), dim3(c->L.block),
+                               c->L.lds_sweep, s, a);
+        else
+            hipLaunchKernelGGL((k_sweep<T, TI, MAXB, BGK, false>), dim3(c->L.n_fast * c->L.n_kc), dim3(c->L.block),
+                               c->L.lds_sweep, s, a);
     }
     if (c->L.n_generic > 0) {
         a.tile_list = c->b.tiles + c->L.n_fast;

@@ -23,7 +23,9 @@
 
 namespace fk {
 
-template <typename T, int TI, int S, bool RAGGED = false, bool BGK = false>
+// STREAM: the tile's inner rows are read with non-temporal loads (see the
+// row loads below); only where every row of f starts on a 128-byte line.
+template <typename T, int TI, int S, bool RAGGED = false, bool BGK = false, bool STREAM = false>
 __device__ __forceinline__ void sweep_fast(const SweepArgs<T>& a, int it, int kci, double* smem, int j, int B)
 {
     const int i0 = it * TI;
@@ -67,11 +69,25 @@ __device__ __forceinline__ void sweep_fast(const SweepArgs<T>& a, int it, int kc
     }
 
     auto plane_in = [&](int kk) { return make_rsrc(a.fin + (size_t)kk * plane, pbytes); };
+    // With STREAM the rows read by this tile alone, the inner rows
+    // 2 .. TI-1, are streamed past L2 (non-temporal loads).  The halo rows
+    // and the tile's first and last rows (the halo rows of the neighbouring
+    // tiles, read again by them) keep the default policy and stay in L2.
+    // Sweep time, default -> inner rows streamed: 4096 x 384 x 384 836.4 ->
+    // 823.3 us; 2048 x 384 x 384 423.4 -> 412.8; 2048 x 256 x 256 194.9 ->
+    // 190.6; the same in FP64 406.9 -> 403.7.  Streaming the first and last
+    // rows too raised the reads at 4096 x 384 x 384 from 1.004x to 1.035x
+    // the algorithmic bytes and gave back most of the gain.  Where rows share
+    // lines with their neighbours (v_y widths off multiples of 32 FP32
+    // values) streaming cost the 64-instance batch 8%, so it follows the
+    // rule of the non-temporal stores.
+    constexpr int kInnerCp = STREAM ? kCpStream : kCpDefault;
     auto ldrow = [&](const rsrc_t& pr, int r) -> T {
         if (r == 0) return bload<T>(pr, vlo, 0);
         if (r == TI + 1) return bload<T>(pr, vhi, 0);
-        if (RAGGED) return bload<T>(pr, roff(r), 0);
-        return bload<T>(pr, vb, (r - 1) * rb);
+        if (r == 1 || r == TI) return RAGGED ? bload<T>(pr, roff(r), 0) : bload<T>(pr, vb, (r - 1) * rb);
+        if (RAGGED) return bload<T, kInnerCp>(pr, roff(r), 0);
+        return bload<T, kInnerCp>(pr, vb, (r - 1) * rb);
     };
 
     // w0/w1: the two planes the row's upwind update reads; w2: prefetch.
@@ -310,14 +326,14 @@ __device__ __forceinline__ void sweep_fast(const SweepArgs<T>& a, int it, int kc
     }
 }
 
-template <typename T, int TI, bool BGK = false>
+template <typename T, int TI, bool BGK = false, bool STREAM = false>
 __device__ __forceinline__ void sweep_fast_dispatch(const SweepArgs<T>& a, int it, int kci, double* smem, int j, int B)
 {
     switch (tile_split(it, TI, a.nvx)) {
-    case 0: sweep_fast<T, TI, 0, false, BGK>(a, it, kci, smem, j, B); break;
-    case 1: sweep_fast<T, TI, 1, false, BGK>(a, it, kci, smem, j, B); break;
-    case TI + 1: sweep_fast<T, TI, TI + 1, false, BGK>(a, it, kci, smem, j, B); break;
-    default: sweep_fast<T, TI, TI + 2, false, BGK>(a, it, kci, smem, j, B); break;
+    case 0: sweep_fast<T, TI, 0, false, BGK, STREAM>(a, it, kci, smem, j, B); break;
+    case 1: sweep_fast<T, TI, 1, false, BGK, STREAM>(a, it, kci, smem, j, B); break;
+    case TI + 1: sweep_fast<T, TI, TI + 1, false, BGK, STREAM>(a, it, kci, smem, j, B); break;
+    default: sweep_fast<T, TI, TI + 2, false, BGK, STREAM>(a, it, kci, smem, j, B); break;
     }
 }
 
@@ -353,14 +369,15 @@ __device__ __forceinline__ void sweep_rest(const SweepArgs<T>& a, int it, int kc
 // Tiles of a launch: blockIdx -> (x chunk, entry of the launch's v_x tile
 // list), remapped so each XCD takes a contiguous range.
 // BGK: compiled with the collision term (a kernel of its own, so the
-// register budget of the plain sweep does not carry it).
-template <typename T, int TI, int MAXB, bool BGK = false>
+// register budget of the plain sweep does not carry it).  STREAM: the inner
+// rows are read with non-temporal loads (rows on 128-byte lines).
+template <typename T, int TI, int MAXB, bool BGK = false, bool STREAM = false>
 __global__ void __launch_bounds__(MAXB) k_sweep(SweepArgs<T> a)
 {
     extern __shared__ double smem[];
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
     const int it = a.tile_list[wg % a.n_list];
-    sweep_fast_dispatch<T, TI, BGK>(a, it, wg / a.n_list, smem, threadIdx.x, blockDim.x);
+    sweep_fast_dispatch<T, TI, BGK, STREAM>(a, it, wg / a.n_list, smem, threadIdx.x, blockDim.x);
 }
 
 template <typename T, int TI, int MAXB, bool BGK = false>
