@@ -437,7 +437,8 @@ int fk_mlp_adamw(fk_mlp* net, double lr, double beta1, double beta2, double eps,
 /* One whole training step on a batch: the forward pass, the loss against
  * target, every gradient and the AdamW step, as fk_mlp_forward,
  * fk_mlp_backward (loss not read back) and fk_mlp_adamw would do it, with
- * fewer launches: the loss and its gradient come out of the output layer's
+ * fewer launches: the first layer's GEMM reads the FP32 features itself,
+ * the loss and its gradient come out of the output layer's
  * GEMM, and one launch forms every weight gradient and applies AdamW to it
  * tile by tile, updates the biases and adds up the loss.  x: device FP32
  * [M][dims[0]]; target: device FP32 [M][dims[n_layers]]; M a multiple of 16

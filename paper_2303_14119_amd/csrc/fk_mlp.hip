@@ -83,8 +83,23 @@ struct GemmPair {
 // column n0 + l%32.  Every thread of the workgroup calls it (one barrier).
 constexpr int kGemmTile = 32;
 
+// The first layer's A operand can come straight from the FP32 features
+// x [M][dx] (zero past column dx, rounded to bf16 as k_mlp_input does)
+// instead of a bf16 copy, which saves the training step the input launch;
+// the tiles of the first column block then store that copy in both layouts
+// (a [M][lda], at [lda][ldat]) for the first layer's weight gradient.
+struct XIn {
+    const float* x;
+    int dx;
+    __bf16* a;
+    int lda;
+    __bf16* at;
+    int ldat;
+};
+
+template <bool XIN = false>
 __device__ __forceinline__ void gemm_nt_tile(const GemmArgs& g, int m0, int n0, float (&part)[4][16][64],
-                                             float (&v)[4])
+                                             float (&v)[4], const XIn& xi = XIn{})
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int ra = m0 + (lane & 31), rb = n0 + (lane & 31);
@@ -105,8 +120,30 @@ __device__ __forceinline__ void gemm_nt_tile(const GemmArgs& g, int m0, int n0, 
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int k0 = 16 * w + 64 * min(s0 + u, nsteps - 1);
-            av[u] = *reinterpret_cast<const bf16x8*>(pa + k0);
+            if constexpr (XIN) {
+                const float* px = xi.x + (size_t)(a_ok ? ra : 0) * xi.dx;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int k = k0 + kk + i;
+                    const float f = px[min(k, xi.dx - 1)];
+                    av[u][i] = (__bf16)(k < xi.dx ? f : 0.0f);
+                }
+            } else {
+                av[u] = *reinterpret_cast<const bf16x8*>(pa + k0);
+            }
             bv[u] = *reinterpret_cast<const bf16x8*>(pb + k0);
+        }
+        if constexpr (XIN) {
+            if (n0 == 0 && a_ok) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (s0 + u < nsteps) {
+                        const int k = 16 * w + 64 * (s0 + u) + kk;
+                        *reinterpret_cast<bf16x8*>(xi.a + (size_t)ra * xi.lda + k) = av[u];
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) xi.at[(size_t)(k + i) * xi.ldat + ra] = av[u][i];
+                    }
+            }
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u)
@@ -124,7 +161,8 @@ __device__ __forceinline__ void gemm_nt_tile(const GemmArgs& g, int m0, int n0, 
     }
 }
 
-__global__ void __launch_bounds__(256) k_gemm_nt(GemmPair gp)
+template <bool XIN = false>
+__global__ void __launch_bounds__(256) k_gemm_nt(GemmPair gp, XIn xi)
 {
     __shared__ float part[4][16][64];       // every wave's partial tile: [wave][element][lane]
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -150,7 +188,7 @@ __global__ void __launch_bounds__(256) k_gemm_nt(GemmPair gp)
         }
     }
     float vv[4];
-    gemm_nt_tile(g, m0, n0, part, vv);
+    gemm_nt_tile<XIN>(g, m0, n0, part, vv, xi);
     if (g.epi == EPI_OUTPUT_LOSS) {
         // every thread reaches the workgroup sum below
         __shared__ double sq_w[4];
@@ -555,8 +593,9 @@ int gemm_tiles(const GemmArgs& g, int* ntn)
     return *ntn * ((g.M + kGemmTile - 1) / kGemmTile);
 }
 
-// one product, or two independent ones in the same launch
-void launch_gemm(const fk_mlp* n, const GemmArgs& g, const GemmArgs* g2 = nullptr)
+// one product, or two independent ones in the same launch; with xi the
+// first layer's product reading the FP32 features itself
+void launch_gemm(const fk_mlp* n, const GemmArgs& g, const GemmArgs* g2 = nullptr, const XIn* xi = nullptr)
 {
     GemmPair gp{};
     gp.p[0] = g;
@@ -568,7 +607,8 @@ void launch_gemm(const fk_mlp* n, const GemmArgs& g, const GemmArgs* g2 = nullpt
     } else {
         gp.ntn[1] = 1;
     }
-    hipLaunchKernelGGL(k_gemm_nt, dim3(tiles), dim3(256), 0, n->stream, gp);
+    if (xi) hipLaunchKernelGGL(k_gemm_nt<true>, dim3(tiles), dim3(256), 0, n->stream, gp, *xi);
+    else hipLaunchKernelGGL(k_gemm_nt<false>, dim3(tiles), dim3(256), 0, n->stream, gp, XIn{});
 }
 
 }  // namespace
@@ -858,12 +898,9 @@ extern "C" int fk_mlp_train_step(fk_mlp* n, const float* x, const float* target,
         return set_error(n ? &n->err : nullptr, FK_E_INVALID,
                          "fk_mlp_train_step: batch a multiple of 16 up to max_batch, step >= 1");
     const int L = n->L, mb = n->max_batch;
-    {
-        const int count = M * n->pad[0];
-        hipLaunchKernelGGL(k_mlp_input, dim3((count + 255) / 256), dim3(256), 0, n->stream, x, M, n->dims[0],
-                           n->pad[0], n->act[0], n->pad[0], n->actT[0], mb);
-    }
-    // forward; the output layer's epilogue forms the loss and dZ_L
+    // forward; the first layer reads the FP32 features itself (and stores
+    // their bf16 copies), the output layer's epilogue forms the loss and dZ_L
+    const XIn xi{x, n->dims[0], n->act[0], n->pad[0], n->actT[0], mb};
     int loss_tiles = 0;
     for (int l = 0; l < L; ++l) {
         GemmArgs g{};
@@ -896,7 +933,7 @@ extern "C" int fk_mlp_train_step(fk_mlp* n, const float* x, const float* target,
             int ntn = 0;
             loss_tiles = gemm_tiles(g, &ntn);
         }
-        launch_gemm(n, g);
+        launch_gemm(n, g, nullptr, l == 0 ? &xi : nullptr);
     }
     // input gradients: dZ_{l-1} = (dZ_l W_l) * gelu'(Z_{l-1}), l = L .. 2 (1-based)
     for (int l = L; l >= 2; --l) {
