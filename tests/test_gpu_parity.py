@@ -180,6 +180,39 @@ def test_tall_tiles_random_state(fk, case):
         compare_state(s.state(), o.record(), 1e-5)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_one_step_equals_the_brute_force_operator(fk, dtype):
+    """One GPU step on a 4 x 4 x 4 grid with every part of the step but the
+    electrons' own space charge (emission, both reflection shares, the band
+    source, the field of sigma alone) against A f + b, the affine one-step
+    map assembled column by column from unit states through the oracle."""
+    cfg = W.config(nx=4, nvx=4, nvy=4, length=1e-3, ey=-5e6, delta_max=2.5, a_max_ev=400.0, j_src=1e7,
+                   physics_mask=W.ALL | W.NOSC, r_refl=0.2, r_inel=0.1, cfl=0.8)
+    sigma = 3e-6
+    o = Oracle(cfg)
+    n = 64
+    o.set_state(np.zeros(o.shape), sigma, 0)
+    o.step(1)
+    b = o.f().ravel().copy()
+    A = np.zeros((n, n))
+    for m in range(n):
+        e = np.zeros(n)
+        e[m] = 1e3
+        o.set_state(e.reshape(o.shape), sigma, 0)
+        o.step(1)
+        A[:, m] = (o.f().ravel() - b) / 1e3
+    f0 = np.random.default_rng(12).random(o.shape) * 1e3
+    if dtype == "f32":
+        f0 = f0.astype(np.float32).astype(np.float64)
+    want = A @ f0.ravel() + b
+    with fk.Solver(cfg, dtype) as s:
+        s.write_state(f0, sigma, 0.0, 0)
+        s.step(1)
+        s.sync()
+        got = s.f().astype(np.float64).ravel()
+    assert rel_l2(got, want) <= (1e-12 if dtype == "f64" else 1e-6)
+
+
 def test_particle_balance_fp64(fk):
     cfg = W.c0()
     with fk.Solver(cfg, "f64", trace_cap=1024) as s:

@@ -366,6 +366,56 @@ def test_one_step_map_is_positive_and_contracting():
     assert np.allclose(o.f().ravel(), A @ (2.0 * u - 0.5 * v), rtol=1e-13, atol=1e-16)
 
 
+def affine_step_cfg(mask=W.ALL | W.NOSC):
+    """A 4 x 4 x 4 grid with every part of the step: the emission row
+    (Eq 15), both reflection shares, the band source on plane 0 and the
+    field of the surface charge alone, so that at fixed sigma one step is an
+    affine map of f."""
+    return W.config(nx=4, nvx=4, nvy=4, length=1e-3, ey=-5e6, delta_max=2.5, a_max_ev=400.0, j_src=1e7,
+                    physics_mask=mask, r_refl=0.2, r_inel=0.1, cfl=0.8)
+
+
+def assemble_affine_step(cfg, sigma, scale=1e3):
+    """The one-step map f -> A f + b of the oracle at fixed sigma, column
+    by column: b from f = 0, column m from a unit state."""
+    o = Oracle(cfg)
+    n = int(np.prod(o.shape))
+    o.set_state(np.zeros(o.shape), sigma, 0)
+    o.step(1)
+    b = o.f().ravel().copy()
+    A = np.zeros((n, n))
+    for m in range(n):
+        e = np.zeros(n)
+        e[m] = scale
+        o.set_state(e.reshape(o.shape), sigma, 0)
+        o.step(1)
+        A[:, m] = (o.f().ravel() - b) / scale
+    return o, A, b
+
+
+def test_full_step_at_fixed_field_is_affine():
+    """Brute force on a 4 x 4 x 4 grid: with the field set by sigma alone,
+    every part of the step (x, v_x and v_y sweeps, emission with the yield
+    table, both reflection shares, the source) is affine in f, so the step of
+    a random state equals the assembled A f + b.  A term that used f
+    non-linearly (a flux scaled by a quantity of the same step, a normalisation
+    taken from f) fails it.  With the electrons' own space charge in the field
+    the map is not affine, and the same check sees it."""
+    o, A, b = assemble_affine_step(affine_step_cfg(), 3e-6)
+    rng = np.random.default_rng(4)
+    for _ in range(3):
+        f = rng.random(o.shape) * 1e3
+        o.set_state(f, 3e-6, 0)
+        o.step(1)
+        assert np.allclose(o.f().ravel(), A @ f.ravel() + b, rtol=1e-12, atol=1e-12 * np.abs(b).max())
+    o2, A2, b2 = assemble_affine_step(affine_step_cfg(W.ALL), 3e-6)
+    f = rng.random(o2.shape) * 1e14
+    o2.set_state(f, 3e-6, 0)
+    o2.step(1)
+    got = o2.f().ravel()
+    assert np.abs(got - (A2 @ f.ravel() + b2)).max() > 1e-6 * np.abs(got).max()
+
+
 def test_mirror_symmetry_without_tangential_field():
     """With E_y = 0 and no (one-sided) source, v_y -> -v_y is a symmetry."""
     cfg = tiny(nx=16, nvx=12, nvy=10, physics_mask=W.X | W.VX | W.SEE | W.SELF, ey=0.0)
