@@ -254,9 +254,9 @@ def main():
                          "paper) instead of the paper's first-order upwind step")
     ap.add_argument("--tile-rows", type=int, default=0, help="v_x rows per tile (0: the library's choice)")
     ap.add_argument("--tile-planes", type=int, default=0, help="x planes per tile (0: the library's choice)")
-    ap.add_argument("--mode", choices=("c1", "batch", "mlp"), default="c1",
-                    help="c1: the headline line (default); batch: the 64-instance batched sweep; "
-                         "mlp: surrogate training steps (both for profiling, one JSON line each)")
+    ap.add_argument("--mode", choices=("single", "batch", "mlp"), default="single",
+                    help="single: one run of --workload, the headline line (default); batch: the 64-instance "
+                         "batched sweep; mlp: surrogate training steps (both for profiling, one JSON line each)")
     args = ap.parse_args()
     if args.sample_every <= 0:
         args.sample_every = 1 if args.steps < 100 else 16

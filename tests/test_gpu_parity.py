@@ -90,13 +90,13 @@ def test_c0_fp32_full_run(fk):
         st, orc = s.state(), o.record()
         errs = {q: rel(st[q], orc[q]) for q in ("g_pe", "g_see")}
         errs["sigma"] = rel(st["sigma"] + st["sigma_lo"], orc["sigma"])
-        print("C0 fp32 errors: f", err_f, errs)
+        print("128x64x64 fp32 errors: f", err_f, errs)
         assert err_f <= 1e-4
         for q, e in errs.items():
             assert e <= 1e-6, (q, e)
         worst = max(rel(g["sigma"] + g["sigma_lo"], r["sigma"]) for g, r in zip(gtr[1:], otr)
                     if abs(r["sigma"]) > 1e-3 * abs(orc["sigma"]))
-        print("C0 fp32 worst sigma error along the trace:", worst)
+        print("128x64x64 fp32 worst sigma error along the trace:", worst)
         assert worst <= 1e-6
 
 

@@ -159,7 +159,7 @@ def test_c0_run_with_the_second_order_scheme(fk, dtype):
         assert gr["step"] == r["step"]
         if abs(r["sigma"]) > 1e-3 * abs(otr[-1]["sigma"]):
             worst = max(worst, rel(gr["sigma"] + gr["sigma_lo"], r["sigma"]))
-    print(dtype, "C0 second order: f", rel_l2(g, o.f()), "worst sigma along the trace", worst)
+    print(dtype, "128x64x64 second order: f", rel_l2(g, o.f()), "worst sigma along the trace", worst)
     assert worst <= tol
     assert rel_l2(g, o.f()) <= (1e-12 if dtype == "f64" else 1e-4)
     orc = o.record()
