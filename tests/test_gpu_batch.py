@@ -177,3 +177,49 @@ def test_c2_sweep_workload_runs(fk):
             st = v.state()
             assert np.isfinite(st["n_total"]) and st["n_total"] > 0
             assert abs(st["resid"]) <= 1e-5 * st["n_total"]
+
+
+def random_batch(seed):
+    """Uneven instances drawn from a seed: shapes up to the batch's widest
+    block, subsets of the step's parts, the collision term on some members,
+    both reflection shares and emission normalisations."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(int(rng.integers(4, 9))):
+        mask = W.ALL if rng.random() < 0.6 else int(rng.choice([W.X | W.VX | W.VY | W.SEE | W.SELF, W.ALL | W.NOSC]))
+        if rng.random() < 0.3:
+            mask |= W.BGK
+        nx = int(rng.integers(1, 60))
+        out.append(W.config(nx=nx, nvx=int(rng.integers(1, 60)), nvy=int(rng.integers(1, 257)), length=nx * 3e-6,
+                            ey=-float(rng.uniform(1e6, 6e6)), delta_max=float(rng.uniform(1.5, 3.0)),
+                            a_max_ev=float(rng.uniform(300, 500)), x_src_lo=1e-6, x_src_hi=5e-6, j_src=1e7,
+                            cfl=0.8, physics_mask=mask, r_refl=float(rng.choice([0.0, 0.2])),
+                            r_inel=float(rng.choice([0.0, 0.1])), emission_norm=int(rng.integers(0, 2)),
+                            t_e_ev=40.0, ln_lambda=10.0))
+    return out
+
+
+@pytest.mark.parametrize("seed,single,threads", [(71, False, 256), (72, True, 256), (73, True, 192)])
+def test_random_batches_match_oracle(fk, seed, single, threads):
+    """Seeded random batches, one per launch mode: every member against the
+    FP64 oracle after 15 steps from a random state and a charged surface."""
+    cfgs = random_batch(seed)
+    steps = 15
+    states = [W.random_state((c["nx"], c["nvx"], c["nvy"]), seed=seed * 100 + m, scale=1e1).astype(np.float32)
+              for m, c in enumerate(cfgs)]
+    with fk.Batch(cfgs, single_launch=single, single_threads=threads) as b:
+        for m, v in enumerate(b.views):
+            v.write_state(states[m], 2e-6, 0.0, 0)
+        b.step(steps)
+        b.sync()
+        outs = [(v.f(), v.state()) for v in b.views]
+    for m, (c, (fb, st)) in enumerate(zip(cfgs, outs)):
+        o = Oracle(c)
+        o.set_state(states[m].astype(np.float64), 2e-6, 0)
+        o.step(steps)
+        orc = o.record()
+        print(seed, m, (c["nx"], c["nvx"], c["nvy"]), c["physics_mask"], rel_l2(fb, o.f()))
+        assert rel_l2(fb, o.f()) < 1e-5, m
+        for q in ("g_pe", "g_see", "n_total"):
+            assert abs(st[q] - orc[q]) <= 1e-5 * abs(orc[q]) + 1e-30, (m, q)
+        assert abs(st["sigma"] + st["sigma_lo"] - orc["sigma"]) <= 1e-5 * abs(orc["sigma"]) + 1e-30, m
