@@ -112,3 +112,39 @@ def test_noalloc_second_order_and_collisions(env, dtype):
         assert np.array_equal(fn, fr), m
         for q in ("step", "sigma", "sigma_lo", "g_pe", "g_see", "g_top", "emitted", "loss_v", "n_total", "resid"):
             assert sn[q] == sr[q], (m, q, sn[q], sr[q])
+
+
+def test_noalloc_random_shapes_in_sequence(env):
+    """Eight seeded random grids in a row (both precisions and schemes,
+    ragged and degenerate shapes, subsets of the step's parts), growing and
+    shrinking from call to call, so every call starts on the scratch array
+    another grid left behind: bitwise the context path each time."""
+    torch, fk = env
+    rng = np.random.default_rng(99)
+    done = 0
+    while done < 8:
+        scheme = int(rng.integers(0, 2))
+        dtype = "f64" if rng.random() < 0.5 else "f32"
+        mask = W.ALL if rng.random() < 0.6 else int(rng.choice([W.X | W.VX | W.VY | W.SEE | W.SELF, W.ALL | W.NOSC]))
+        if scheme == 0 and rng.random() < 0.3:
+            mask |= W.BGK
+        nx = int(rng.integers(1, 80))
+        cfg = W.config(nx=nx, nvx=int(rng.integers(1, 70)), nvy=int(rng.integers(1, 300)), length=nx * 3e-6,
+                       ey=-float(rng.uniform(1e6, 6e6)), delta_max=2.5, a_max_ev=400.0, x_src_lo=1e-6,
+                       x_src_hi=5e-6, j_src=1e7, cfl=0.8, physics_mask=mask, r_refl=float(rng.choice([0.0, 0.2])),
+                       r_inel=float(rng.choice([0.0, 0.1])), t_e_ev=40.0, ln_lambda=10.0, scheme=scheme)
+        try:
+            fk.validate(fk.make_params(cfg, dtype))
+        except fk.FlashkinError:
+            continue
+        steps = int(rng.integers(1, 12))
+        f0 = W.random_state((cfg["nx"], cfg["nvx"], cfg["nvy"]), seed=200 + done, scale=1e3)
+        f0 = f0.astype(np.float32 if dtype == "f32" else np.float64)
+        fr, sr = context_run(torch, fk, cfg, dtype, f0, 2e-6, steps)
+        fn, sn, flags = noalloc_run(torch, fk, cfg, dtype, f0, 2e-6, steps)
+        print(done, (cfg["nx"], cfg["nvx"], cfg["nvy"]), dtype, "scheme", scheme, "mask", mask, "steps", steps)
+        assert flags == 0
+        assert np.array_equal(fn, fr), done
+        for q in ("step", "sigma", "sigma_lo", "g_pe", "g_see", "g_top", "emitted", "loss_v", "n_total", "resid"):
+            assert sn[q] == sr[q], (done, q, sn[q], sr[q])
+        done += 1
