@@ -221,3 +221,35 @@ def test_train_step_trains_like_the_separate_calls(env):
     assert f0 == pytest.approx(s0, rel=1e-5)
     assert f1 < 0.1 * f0
     assert abs(f1 - s1) < 0.1 * s1
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4, 5, 6])
+def test_random_networks_train_step(env, seed):
+    """Seeded random network shapes (one to five layers, widths 1 to 300,
+    batches of 16 to 128 rows): the training step's loss and every gradient
+    against the oracle (1e-2) and its AdamW step against the oracle's step
+    applied to its own gradients."""
+    torch, fk = env
+    rng = np.random.default_rng(seed)
+    depth = int(rng.integers(1, 6))
+    dims = [int(rng.integers(1, 12))] + [int(rng.integers(1, 301)) for _ in range(depth - 1)] + [int(rng.integers(1, 200))]
+    m = 16 * int(rng.integers(1, 9))
+    p, x, t = make_case(dims, m, seed=100 + seed)
+    net = fk.MLP(dims, max_batch=max(m, 64))
+    net.set_params(p)
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    net.take_loss()
+    net.train_step(xd.data_ptr(), td.data_ptr(), m, 1, lr=1e-3, weight_decay=0.01)
+    loss, count = net.take_loss()
+    g = net.grads()
+    loss_ref, g_ref = omlp.loss_and_grads(p, dims, x, t)
+    print(dims, m, "loss", loss, loss_ref)
+    assert count == 1 and abs(loss - loss_ref) < 1e-2 * loss_ref
+    for l, (sw, sb) in enumerate(layer_slices(dims)):
+        ew, eb = rel_l2(g[sw], g_ref[sw]), rel_l2(g[sb], g_ref[sb])
+        print("  layer", l, ew, eb)
+        assert ew < 1e-2 and eb < 1e-2, (l, ew, eb)
+    z = np.zeros(p.size)
+    want, _, _ = omlp.adamw(p.astype(np.float64), g.astype(np.float64), z, z, 1, dims, 1e-3, 0.9, 0.999, 1e-8, 0.01)
+    assert np.allclose(net.params().astype(np.float64), want, rtol=2e-6, atol=1e-7)
+    net.close()
