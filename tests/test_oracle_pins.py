@@ -416,6 +416,24 @@ def test_full_step_at_fixed_field_is_affine():
     assert np.abs(got - (A2 @ f.ravel() + b2)).max() > 1e-6 * np.abs(got).max()
 
 
+def test_sigma_telescopes_over_the_fluxes_of_each_step():
+    """Eq 18 summed over the run: sigma after N steps is sigma^0 plus
+    e dt (Gamma_see^n - Gamma_pe^n) over the fluxes of f^0 .. f^(N-1), the
+    fluxes each step's record holds.  The oracle adds the increments in
+    plain FP64, so the exact sum (math.fsum) agrees to N roundings; taking
+    the fluxes one step late, or dropping a step's increment, moves sigma
+    by far more."""
+    o = Oracle(W.c0())
+    recs = [o.record()] + o.step(400, trace=True)
+    terms = [E_CHARGE * o.dt * (r["g_see"] - r["g_pe"]) for r in recs[:-1]]
+    want = math.fsum([recs[0]["sigma"]] + terms)
+    got = recs[-1]["sigma"]
+    scale = math.fsum(abs(t) for t in terms)
+    assert abs(got - want) <= 400 * 2.3e-16 * scale
+    late = math.fsum([recs[0]["sigma"]] + [E_CHARGE * o.dt * (r["g_see"] - r["g_pe"]) for r in recs[1:]])
+    assert abs(late - got) > 1e-6 * abs(got)
+
+
 def test_mirror_symmetry_without_tangential_field():
     """With E_y = 0 and no (one-sided) source, v_y -> -v_y is a symmetry."""
     cfg = tiny(nx=16, nvx=12, nvy=10, physics_mask=W.X | W.VX | W.SEE | W.SELF, ey=0.0)
