@@ -446,7 +446,8 @@ __global__ void k_weight_copies(const float* __restrict__ w, int count, int ld, 
 
 // ---------------------------------------------------------- training step
 // A whole training step in fewer launches (fk_mlp_train_step): the forward
-// GEMMs, the output GEMM with the loss and its gradient in its epilogue
+// GEMMs (the first reading the FP32 features itself), the output GEMM with
+// the loss and its gradient in its epilogue
 // (per-tile sums of squared errors), the input-gradient GEMMs, then one
 // launch for every weight gradient dW_l = dZ_{l+1}^T A_l as 32 x 32 tiles
 // (K = the batch, the four-wave tile of k_gemm_nt), each tile written and
